@@ -1,0 +1,178 @@
+/*
+ * cwt.h — C ABI of the MI355X (gfx950) FFT-based Morlet continuous wavelet
+ * transform library (libcwt.so).
+ *
+ * The method (Nakanishi, arXiv 2506.07793, section "Fourier transformed
+ * formula"): one forward FFT per channel of the zero-padded signal, a
+ * multiplication by the closed-form Fourier transform of the wavelet at every
+ * analysis frequency (Morlet and Gabor equations of the same section), and one
+ * inverse FFT per (channel, frequency); the result is complex, or its power
+ * |W|^2 (section "Precision"), or the mean power of EEG bands (introduction).
+ * Padding follows section "Fast Fourier transform": the smallest length >= n
+ * whose prime factors are 2, 3, 5 and 7.
+ *
+ * Conventions shared by every call:
+ *   - Every function returns CWT_OK (0) or a negative CWT_E_* code; a
+ *     thread-local message is available from cwt_last_error().  No C++
+ *     exception crosses this boundary.
+ *   - Arguments are validated before any device memory is allocated, written
+ *     or any kernel is launched; on error nothing has been enqueued.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is enqueued asynchronously on it; no call synchronises the
+ *     host unless stated.
+ *   - Device pointers are caller-owned unless stated; the library never
+ *     frees them.
+ *   - Distinct objects may be used from different threads concurrently; one
+ *     object must not be used from two threads at once unless stated.
+ *   - Only gfx950 devices are supported (CWT_E_UNSUPPORTED otherwise).
+ */
+#ifndef CWT_H
+#define CWT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define CWT_OK 0
+#define CWT_E_INVALID (-1)     /* bad argument; nothing was enqueued          */
+#define CWT_E_UNSUPPORTED (-2) /* valid request beyond this build's limits     */
+#define CWT_E_NOMEM (-3)       /* a device or host allocation failed           */
+#define CWT_E_HIP (-4)         /* a HIP runtime call failed (name in message)  */
+#define CWT_E_BUDGET (-5)      /* admission would exceed the HBM budget        */
+#define CWT_E_AGAIN (-6)       /* nothing ready / queue full; retry later      */
+
+/* ---- plan options ---------------------------------------------------- */
+enum cwt_wavelet { CWT_WAVELET_MORLET = 0, CWT_WAVELET_GABOR = 1 };
+enum cwt_pad { CWT_PAD_SMOOTH7 = 0, CWT_PAD_POW2 = 1, CWT_PAD_NONE = 2, CWT_PAD_EXPLICIT = 3 };
+enum cwt_out { CWT_OUT_COMPLEX64 = 0, CWT_OUT_POWER_F32 = 1, CWT_OUT_BANDPOWER_F32 = 2 };
+enum cwt_precision {
+    CWT_PREC_FP32 = 0,       /* FP32 radix-2/3/4/5/7/8/16 FFT in LDS               */
+    CWT_PREC_SPLIT_F16 = 1,  /* DFT-as-GEMM radix stages on FP16 MFMA, hi+lo split  */
+    CWT_PREC_SPLIT_BF16 = 2  /* DFT-as-GEMM radix stages on BF16 MFMA, hi+lo split  */
+};
+
+/* Largest padded length one workgroup holds in LDS (complex64, 160 KB). */
+#define CWT_MAX_LEN 20480
+#define CWT_MAX_FREQS 4096
+#define CWT_MAX_BANDS 16
+
+typedef struct cwt_plan_opts {
+    int32_t wavelet;          /* enum cwt_wavelet                                  */
+    int32_t pad;              /* enum cwt_pad                                      */
+    int64_t explicit_len;     /* padded length when pad == CWT_PAD_EXPLICIT (>= n) */
+    int32_t out;              /* enum cwt_out                                      */
+    int32_t precision;        /* enum cwt_precision                                */
+    int32_t n_bands;          /* 0 = the five default EEG bands                    */
+    const double *band_edges; /* 2*n_bands values (lo0, hi0, lo1, hi1, ...) in Hz.
+                                 A frequency f belongs to band k when
+                                 lo_k <= f < hi_k, or f == hi_k for the last band.
+                                 Defaults: delta 1-4, theta 4-8, alpha 8-13,
+                                 beta 13-30, gamma 30-100 Hz.  Copied at create. */
+} cwt_plan_opts;
+
+/* Fill *opts with the defaults: Morlet, SMOOTH7, complex64, FP32, default bands. */
+int cwt_plan_opts_init(cwt_plan_opts *opts);
+
+typedef struct cwt_plan cwt_plan;
+
+/*
+ * Create an immutable plan for signals of n samples at sfreq Hz, analysed at
+ * n_freqs frequencies freqs[] (Hz).  The wavelet parameter sigma (the paper's
+ * Morlet sigma, equal to the number of cycles and to omega0) is n_cycles[i]
+ * per frequency, or omega0 for every frequency when n_cycles is NULL.
+ *
+ * Validation (CWT_E_INVALID): out != NULL; n >= 1; sfreq finite and > 0;
+ * 1 <= n_freqs <= CWT_MAX_FREQS; every frequency finite with
+ * 0 < f < sfreq / 2; every sigma finite and > 0; known enum values; for
+ * CWT_PAD_EXPLICIT explicit_len >= n; for band output every band has
+ * lo < hi and owns at least one frequency, and n_bands <= CWT_MAX_BANDS.
+ * A padded length above CWT_MAX_LEN, or whose prime factors are not all in
+ * {2, 3, 5, 7}, gives CWT_E_UNSUPPORTED.
+ *
+ * On success the plan owns device memory for the wavelet spectra (FP64
+ * evaluation on the GPU, rounded once to FP32, 1/L folded in, only the bins
+ * whose magnitude is at least 1e-12 of the peak) and the twiddle table
+ * exp(2 pi i m / L) (FP64 on the GPU, rounded once).  Their generation is
+ * enqueued on `stream`; the plan may be used on any stream once `stream` has
+ * reached that point (cwt_plan_create does not synchronise).
+ */
+int cwt_plan_create(cwt_plan **out, int64_t n, double sfreq, const double *freqs,
+                    int32_t n_freqs, const double *n_cycles, double omega0,
+                    const cwt_plan_opts *opts, void *stream);
+
+typedef struct cwt_plan_desc {
+    int64_t n;               /* samples per channel                            */
+    int64_t L;               /* padded FFT length                              */
+    int64_t n_freqs;
+    int64_t n_bands;         /* rows per channel in band mode                  */
+    int32_t out;             /* enum cwt_out                                   */
+    int32_t precision;       /* enum cwt_precision                             */
+    int32_t wavelet;
+    int32_t threads;         /* threads per workgroup of the transform kernel  */
+    int32_t n_passes;        /* radix passes                                    */
+    int32_t radix[16];       /* radix of each pass                              */
+    int64_t out_rows;        /* rows per channel: n_freqs, or n_bands            */
+    int64_t out_elem_bytes;  /* 8 (complex64) or 4 (float32)                     */
+    int64_t spectrum_bins;   /* total stored wavelet-spectrum bins (all freqs)   */
+    int64_t max_band_bins;   /* widest stored spectrum band                      */
+} cwt_plan_desc;
+
+int cwt_plan_info(const cwt_plan *plan, cwt_plan_desc *desc);
+
+/*
+ * Validate a plan request and describe the plan cwt_plan_create would make
+ * (padded length, radix schedule, stored spectrum bins) without touching
+ * the device or allocating anything.  Same arguments and validation as
+ * cwt_plan_create; needs no GPU.
+ */
+int cwt_plan_describe(cwt_plan_desc *desc, int64_t n, double sfreq, const double *freqs,
+                      int32_t n_freqs, const double *n_cycles, double omega0,
+                      const cwt_plan_opts *opts);
+
+/* Lower and upper band-membership of each frequency: band_of_freq[i] is the
+ * band index of frequency i, or -1 when it belongs to none (n_freqs ints). */
+int cwt_plan_band_of_freq(const cwt_plan *plan, int32_t *band_of_freq);
+
+/* Device workspace bytes cwt_execute needs for C channels (per-channel
+ * half spectra, 256-byte aligned).  Returns 0 on invalid arguments. */
+size_t cwt_workspace_size(const cwt_plan *plan, int64_t C);
+
+/*
+ * Transform C channels.  x: device float32 [C][n] row-major.  out: device
+ * [C][n_freqs][n] complex64 (interleaved re, im) or float32 power, or
+ * [C][n_bands][n] float32 band power, fully overwritten.  ws: device
+ * workspace of at least cwt_workspace_size(plan, C) bytes, 256-byte aligned.
+ * x, out and ws must not overlap.  Asynchronous on `stream`; the plan may be
+ * executed concurrently on several streams, each with its own ws and out.
+ * C == 0 is a no-op.
+ */
+int cwt_execute(const cwt_plan *plan, const float *x, int64_t C, void *out, void *ws,
+                size_t ws_bytes, void *stream);
+
+/*
+ * Copy the plan's tables to host memory for inspection (synchronises
+ * `stream`).  H_host receives spectrum_bins floats (the stored bins of every
+ * frequency, frequency after frequency); band_host receives 3 ints per
+ * frequency (first signed bin, number of bins, offset into H_host); tw_host
+ * receives 2*L floats (the twiddle table).  Any pointer may be NULL.
+ */
+int cwt_plan_copy_tables(const cwt_plan *plan, float *H_host, int32_t *band_host,
+                         float *tw_host, void *stream);
+
+/* Release the plan.  Synchronises `stream` first, so work already enqueued
+ * on it that uses the plan completes before the tables are freed; work on
+ * other streams that uses the plan must be complete before this call. */
+int cwt_plan_destroy(cwt_plan *plan, void *stream);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *cwt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CWT_H */

@@ -1,0 +1,196 @@
+"""MI355X-native FFT-based Morlet continuous wavelet transform (gfx950 HIP).
+
+Python binding of libcwt (include/cwt.h).  torch supplies device memory and
+streams; every step of the transform runs in libcwt's HIP kernels.
+
+    import torch, paper_2506_07793_amd as cwt
+    plan = cwt.Plan(n=4096, sfreq=1000.0, freqs=freqs, n_cycles=cyc)
+    W = plan.execute(x)          # x: cuda float32 [C, n] -> complex64 [C, F, n]
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import CwtError  # noqa: F401
+
+__all__ = ["Plan", "CwtError", "cwt", "describe", "DEFAULT_BANDS"]
+
+DEFAULT_BANDS = ((1.0, 4.0), (4.0, 8.0), (8.0, 13.0), (13.0, 30.0), (30.0, 100.0))
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        if not torch.cuda.is_available():
+            return ctypes.c_void_p(0)
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _make_opts(lib, wavelet, pad, explicit_len, out, precision, bands):
+    opts = _lib.PlanOpts()
+    lib.cwt_plan_opts_init(ctypes.byref(opts))
+    opts.wavelet = _lib.WAVELET[wavelet]
+    opts.pad = _lib.PAD[pad]
+    opts.explicit_len = int(explicit_len)
+    opts.out = _lib.OUT[out]
+    opts.precision = _lib.PRECISION[precision]
+    edges = None
+    if bands is not None:
+        edges = np.ascontiguousarray(np.asarray(bands, dtype=np.float64).ravel())
+        opts.n_bands = len(edges) // 2
+        opts.band_edges = edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return opts, edges
+
+
+def _cycles(freqs, n_cycles, omega0):
+    if n_cycles is not None:
+        cyc = np.asarray(n_cycles, dtype=np.float64)
+        if cyc.ndim == 0:
+            cyc = np.full(freqs.shape, float(cyc))
+        cyc = np.ascontiguousarray(cyc.ravel())
+        return cyc, cyc.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0.0
+    if omega0 is None:
+        raise ValueError("give n_cycles or omega0")
+    return None, None, float(omega0)
+
+
+def describe(n, sfreq, freqs, n_cycles=None, omega0=None, wavelet="morlet", pad="smooth7",
+             explicit_len=0, out="complex64", precision="fp32", bands=None):
+    """Validate a plan request and describe it without a GPU (cwt_plan_describe)."""
+    lib = _lib.load()
+    freqs = np.ascontiguousarray(np.asarray(freqs, dtype=np.float64).ravel())
+    opts, edges = _make_opts(lib, wavelet, pad, explicit_len, out, precision, bands)
+    cyc, cyc_ptr, om = _cycles(freqs, n_cycles, omega0)
+    desc = _lib.PlanDesc()
+    _lib.check(lib.cwt_plan_describe(ctypes.byref(desc), int(n), float(sfreq),
+                                     freqs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     len(freqs), cyc_ptr, om, ctypes.byref(opts)))
+    return desc
+
+
+class Plan:
+    """A CWT plan: padded length, radix schedule and device-resident tables.
+
+    n_cycles: one sigma per frequency (the paper's Morlet sigma), or None to
+    use omega0 for every frequency.  out: "complex64", "power" or "bandpower".
+    """
+
+    def __init__(self, n, sfreq, freqs, n_cycles=None, omega0=None, wavelet="morlet",
+                 pad="smooth7", explicit_len=0, out="complex64", precision="fp32", bands=None,
+                 stream=None):
+        lib = _lib.load()
+        self._lib = lib
+        self.freqs = np.ascontiguousarray(np.asarray(freqs, dtype=np.float64).ravel())
+        opts, self._edges = _make_opts(lib, wavelet, pad, explicit_len, out, precision, bands)
+        self._cyc, cyc_ptr, om = _cycles(self.freqs, n_cycles, omega0)
+        handle = ctypes.c_void_p()
+        self._ptr = None
+        _lib.check(lib.cwt_plan_create(
+            ctypes.byref(handle), int(n), float(sfreq),
+            self.freqs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(self.freqs),
+            cyc_ptr, om, ctypes.byref(opts), _stream_handle(stream)))
+        self._ptr = handle
+        desc = _lib.PlanDesc()
+        _lib.check(lib.cwt_plan_info(self._ptr, ctypes.byref(desc)))
+        self.desc = desc
+        self.n = int(desc.n)
+        self.L = int(desc.L)
+        self.n_freqs = int(desc.n_freqs)
+        self.n_bands = int(desc.n_bands)
+        self.out_rows = int(desc.out_rows)
+        self.out_mode = out
+        self.sfreq = float(sfreq)
+
+    # -- info ------------------------------------------------------------
+    @property
+    def radices(self):
+        return [int(self.desc.radix[i]) for i in range(self.desc.n_passes)]
+
+    def band_of_freq(self):
+        out = np.empty(self.n_freqs, dtype=np.int32)
+        _lib.check(self._lib.cwt_plan_band_of_freq(
+            self._ptr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return out
+
+    def workspace_size(self, C):
+        return int(self._lib.cwt_workspace_size(self._ptr, int(C)))
+
+    def tables(self, stream=None):
+        """(H bins [spectrum_bins] f32, band [F,3] int32, twiddles [L] complex64) on the host."""
+        H = np.empty(max(1, int(self.desc.spectrum_bins)), dtype=np.float32)
+        band = np.empty((self.n_freqs, 3), dtype=np.int32)
+        tw = np.empty(2 * self.L, dtype=np.float32)
+        _lib.check(self._lib.cwt_plan_copy_tables(
+            self._ptr, H.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+            band.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            tw.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream_handle(stream)))
+        return H[: int(self.desc.spectrum_bins)], band, tw.view(np.complex64)
+
+    # -- execution -------------------------------------------------------
+    def output_shape(self, C):
+        return (int(C), self.out_rows, self.n)
+
+    def alloc_output(self, C, device="cuda"):
+        import torch
+        dt = torch.complex64 if self.out_mode == "complex64" else torch.float32
+        return torch.empty(self.output_shape(C), dtype=dt, device=device)
+
+    def alloc_workspace(self, C, device="cuda"):
+        import torch
+        nbytes = max(256, self.workspace_size(C))
+        return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+    def execute(self, x, out=None, ws=None, stream=None):
+        """x: cuda float32 [C, n] (or [n]).  Returns the output tensor."""
+        import torch
+        if x.dim() == 1:
+            x = x[None, :]
+        if x.dtype != torch.float32 or not x.is_cuda:
+            raise TypeError("x must be a cuda float32 tensor")
+        if x.shape[-1] != self.n:
+            raise ValueError("x has %d samples, plan expects %d" % (x.shape[-1], self.n))
+        x = x.contiguous()
+        C = int(x.shape[0])
+        if out is None:
+            out = self.alloc_output(C, device=x.device)
+        if tuple(out.shape) != self.output_shape(C) or not out.is_contiguous():
+            raise ValueError("out must be contiguous with shape %s" % (self.output_shape(C),))
+        if ws is None:
+            ws = self.alloc_workspace(C, device=x.device)
+        _lib.check(self._lib.cwt_execute(self._ptr, _dptr(x), C, _dptr(out), _dptr(ws),
+                                         ws.numel() * ws.element_size(), _stream_handle(stream)))
+        return out
+
+    def close(self, stream=None):
+        if getattr(self, "_ptr", None):
+            try:
+                self._lib.cwt_plan_destroy(self._ptr, _stream_handle(stream))
+            finally:
+                self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._ptr
+
+
+def cwt(x, sfreq, freqs, n_cycles, **kw):
+    """One-shot transform of a cuda float32 [C, n] tensor."""
+    plan = Plan(x.shape[-1], sfreq, freqs, n_cycles=n_cycles, **kw)
+    try:
+        return plan.execute(x)
+    finally:
+        import torch
+        torch.cuda.current_stream().synchronize()
+        plan.close()

@@ -1,0 +1,545 @@
+// C ABI of libcwt: validation, planning (padded length, radix schedule,
+// spectrum bands, band groups), device tables and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/cwt.h"
+#include "cwt_internal.hpp"
+#include "cwt_kernels.hpp"
+
+using namespace cwtk;
+
+// ------------------------------------------------------------ errors --
+
+static thread_local std::string g_last_error;
+
+namespace cwtrt {
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(CWT_E_HIP, "%s: %s (%s)", what, hipGetErrorName(e), hipGetErrorString(e));
+}
+
+void clear_error() { g_last_error.clear(); }
+
+// ----------------------------------------------------------- planning --
+
+static bool smooth7(int64_t m)
+{
+    if (m < 1) return false;
+    for (int p : {2, 3, 5, 7})
+        while (m % p == 0) m /= p;
+    return m == 1;
+}
+
+int64_t pad_length(int64_t n, int mode, int64_t explicit_len)
+{
+    switch (mode) {
+    case CWT_PAD_SMOOTH7: {
+        int64_t m = n;
+        while (!smooth7(m)) ++m;
+        return m;
+    }
+    case CWT_PAD_POW2: {
+        int64_t m = 1;
+        while (m < n) m <<= 1;
+        return m;
+    }
+    case CWT_PAD_NONE: return n;
+    case CWT_PAD_EXPLICIT: return explicit_len;
+    default: return -1;
+    }
+}
+
+// Radix schedule: the largest radices first (16, 8, 4, 2, then 7, 5, 3),
+// falling back to schedules without 16 (then without 8) when a thread of a
+// 1024-wide workgroup would have to hold too many values.  The workgroup size
+// is the smallest multiple of 64 (at least L/16) for which no thread holds
+// more than maxv values in any pass; maxv is 16 when possible, else 24.
+static bool try_radix_plan(int L, const int *order, int n_order, int maxv, RadixPlan &rp)
+{
+    rp = RadixPlan{};
+    rp.L = L;
+    int m = L;
+    int np = 0;
+    for (int oi = 0; oi < n_order; ++oi) {
+        const int r = order[oi];
+        while (m % r == 0) {
+            if (np >= kMaxPasses) return false;
+            rp.radix[np++] = r;
+            m /= r;
+        }
+    }
+    if (m != 1) return false;
+    if (np == 0) rp.radix[np++] = 1;  // L == 1: a single identity pass
+    rp.n_pass = np;
+    for (int T = std::max(64, std::min(1024, ((L / 16 + 63) / 64) * 64)); T <= 1024; T += 64) {
+        bool ok = true;
+        for (int i = 0; i < np && ok; ++i) {
+            const int R = rp.radix[i];
+            const int S = L / R;
+            const int nb = (S + T - 1) / T;
+            const int mb = std::max(1, maxv / R);
+            if (nb > mb) ok = false;
+        }
+        if (ok) {
+            rp.threads = T;
+            rp.maxv = maxv;
+            return true;
+        }
+    }
+    return false;
+}
+
+bool make_radix_plan(int L, RadixPlan &rp)
+{
+    static const int o1[] = {16, 8, 4, 2, 7, 5, 3};
+    static const int o2[] = {8, 4, 2, 7, 5, 3};
+    static const int o3[] = {4, 2, 7, 5, 3};
+    for (int maxv : {16, 24}) {
+        if (try_radix_plan(L, o1, 7, maxv, rp)) return true;
+        if (try_radix_plan(L, o2, 6, maxv, rp)) return true;
+        if (try_radix_plan(L, o3, 5, maxv, rp)) return true;
+    }
+    return false;
+}
+
+// Stored band of one frequency's spectrum: every signed bin whose value can
+// reach 1e-12 of the spectrum's main Gaussian (and, for Morlet, of the
+// kappa-weighted Gaussian at zero frequency).
+BandDesc spectrum_band(int L, double sfreq, double f, double sigma, int wavelet)
+{
+    const double eps = 1e-12;
+    const double xm = std::sqrt(2.0 * std::log(1.0 / eps));
+    double ulo = sigma - xm, uhi = sigma + xm;
+    if (wavelet == CWT_WAVELET_MORLET) {
+        const double kappa = std::exp(-0.5 * sigma * sigma);
+        if (kappa > eps) {
+            const double xk = std::sqrt(2.0 * std::log(kappa / eps));
+            ulo = std::min(ulo, -xk);
+        }
+    }
+    // u = s omega, omega = 2 pi sfreq b / L, s = sigma / (2 pi f)
+    const double per_bin = sigma * sfreq / (f * (double)L);
+    double blo = std::floor(ulo / per_bin) - 1.0;
+    double bhi = std::ceil(uhi / per_bin) + 1.0;
+    const double min_b = -(double)(L / 2);
+    const double max_b = (double)((L + 1) / 2 - 1);
+    blo = std::max(blo, min_b);
+    bhi = std::min(bhi, max_b);
+    BandDesc bd{};
+    if (bhi < blo) {  // entirely outside the representable bins
+        bd.lo = 0;
+        bd.K = 0;
+    } else {
+        bd.lo = (int)blo;
+        bd.K = (int)(bhi - blo) + 1;
+    }
+    return bd;
+}
+
+}  // namespace cwtrt
+
+using namespace cwtrt;
+
+// --------------------------------------------------------------- ABI --
+
+static const double kDefaultBands[10] = {1.0, 4.0, 4.0, 8.0, 8.0, 13.0, 13.0, 30.0, 30.0, 100.0};
+
+extern "C" int cwt_plan_opts_init(cwt_plan_opts *o)
+{
+    if (!o) return fail(CWT_E_INVALID, "cwt_plan_opts_init: opts is NULL");
+    std::memset(o, 0, sizeof *o);
+    o->wavelet = CWT_WAVELET_MORLET;
+    o->pad = CWT_PAD_SMOOTH7;
+    o->out = CWT_OUT_COMPLEX64;
+    o->precision = CWT_PREC_FP32;
+    return CWT_OK;
+}
+
+extern "C" const char *cwt_last_error(void) { return g_last_error.c_str(); }
+
+namespace cwtrt {
+
+// Validation shared with other entry points: everything about the request
+// that does not need the device.  Fills the host-side parts of the plan.
+int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
+                      int32_t n_freqs, const double *n_cycles, double omega0,
+                      const cwt_plan_opts *opts_in)
+{
+    cwt_plan_opts o;
+    cwt_plan_opts_init(&o);
+    if (opts_in) o = *opts_in;
+    if (n < 1) return fail(CWT_E_INVALID, "n must be >= 1 (got %lld)", (long long)n);
+    if (!std::isfinite(sfreq) || sfreq <= 0)
+        return fail(CWT_E_INVALID, "sfreq must be finite and > 0");
+    if (n_freqs < 1 || n_freqs > CWT_MAX_FREQS)
+        return fail(CWT_E_INVALID, "n_freqs must be in [1, %d] (got %d)", CWT_MAX_FREQS, n_freqs);
+    if (!freqs) return fail(CWT_E_INVALID, "freqs is NULL");
+    if (o.wavelet != CWT_WAVELET_MORLET && o.wavelet != CWT_WAVELET_GABOR)
+        return fail(CWT_E_INVALID, "unknown wavelet %d", o.wavelet);
+    if (o.pad < CWT_PAD_SMOOTH7 || o.pad > CWT_PAD_EXPLICIT)
+        return fail(CWT_E_INVALID, "unknown pad mode %d", o.pad);
+    if (o.out < CWT_OUT_COMPLEX64 || o.out > CWT_OUT_BANDPOWER_F32)
+        return fail(CWT_E_INVALID, "unknown output mode %d", o.out);
+    if (o.precision < CWT_PREC_FP32 || o.precision > CWT_PREC_SPLIT_BF16)
+        return fail(CWT_E_INVALID, "unknown precision %d", o.precision);
+    if (o.pad == CWT_PAD_EXPLICIT && o.explicit_len < n)
+        return fail(CWT_E_INVALID, "explicit_len %lld < n %lld", (long long)o.explicit_len,
+                    (long long)n);
+    P.freqs.assign(freqs, freqs + n_freqs);
+    P.sigmas.resize(n_freqs);
+    for (int i = 0; i < n_freqs; ++i) {
+        const double f = freqs[i];
+        if (!std::isfinite(f) || f <= 0 || f >= 0.5 * sfreq)
+            return fail(CWT_E_INVALID, "freqs[%d] = %g outside (0, sfreq/2 = %g)", i, f,
+                        0.5 * sfreq);
+        const double s = n_cycles ? n_cycles[i] : omega0;
+        if (!std::isfinite(s) || s <= 0)
+            return fail(CWT_E_INVALID, "n_cycles/omega0 for freqs[%d] must be finite and > 0", i);
+        P.sigmas[i] = s;
+    }
+    // bands
+    P.band_of_freq.assign(n_freqs, -1);
+    if (o.out == CWT_OUT_BANDPOWER_F32) {
+        const double *edges = kDefaultBands;
+        int nb = 5;
+        if (o.n_bands != 0) {
+            if (o.n_bands < 0 || o.n_bands > CWT_MAX_BANDS)
+                return fail(CWT_E_INVALID, "n_bands must be in [1, %d]", CWT_MAX_BANDS);
+            if (!o.band_edges) return fail(CWT_E_INVALID, "band_edges is NULL");
+            edges = o.band_edges;
+            nb = o.n_bands;
+        }
+        P.band_edges.assign(edges, edges + 2 * nb);
+        P.grp_off.assign(1, 0);
+        P.grp_freq.clear();
+        for (int b = 0; b < nb; ++b) {
+            const double lo = edges[2 * b], hi = edges[2 * b + 1];
+            if (!std::isfinite(lo) || !std::isfinite(hi) || !(lo < hi))
+                return fail(CWT_E_INVALID, "band %d has lo >= hi or non-finite edges", b);
+            for (int i = 0; i < n_freqs; ++i) {
+                const double f = freqs[i];
+                const bool in = (f >= lo && f < hi) || (b == nb - 1 && f == hi);
+                if (in) {
+                    P.grp_freq.push_back(i);
+                    if (P.band_of_freq[i] < 0) P.band_of_freq[i] = b;
+                }
+            }
+            if ((int)P.grp_freq.size() == P.grp_off.back())
+                return fail(CWT_E_INVALID, "band %d [%g, %g) owns no frequency", b, lo, hi);
+            P.grp_off.push_back((int)P.grp_freq.size());
+        }
+        P.n_bands = nb;
+    } else {
+        P.n_bands = 0;
+    }
+    const int64_t L = pad_length(n, o.pad, o.explicit_len);
+    if (L > CWT_MAX_LEN)
+        return fail(CWT_E_UNSUPPORTED, "padded length %lld exceeds the LDS limit %d",
+                    (long long)L, CWT_MAX_LEN);
+    if (!smooth7(L))
+        return fail(CWT_E_UNSUPPORTED,
+                    "padded length %lld has a prime factor above 7 (use SMOOTH7 or POW2)",
+                    (long long)L);
+    if (!make_radix_plan((int)L, P.rp))
+        return fail(CWT_E_UNSUPPORTED, "no radix schedule fits length %lld in one workgroup",
+                    (long long)L);
+    P.n = n;
+    P.sfreq = sfreq;
+    P.L = (int)L;
+    P.F = n_freqs;
+    P.opts = o;
+    P.opts.band_edges = nullptr;
+    // spectrum bands
+    P.bands.resize(n_freqs);
+    int off = 0, maxK = 0;
+    for (int i = 0; i < n_freqs; ++i) {
+        BandDesc bd = spectrum_band(P.L, sfreq, freqs[i], P.sigmas[i], o.wavelet);
+        bd.off = off;
+        off += bd.K;
+        maxK = std::max(maxK, bd.K);
+        P.bands[i] = bd;
+    }
+    P.total_bins = off;
+    P.max_bins = maxK;
+    return CWT_OK;
+}
+
+int check_device(int *dev_out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(CWT_E_UNSUPPORTED, "device %d is %s; this library is built for gfx950", dev,
+                    prop.gcnArchName);
+    if (dev_out) *dev_out = dev;
+    return CWT_OK;
+}
+
+template <class T>
+static int dev_upload(T **dst, const T *src, size_t count, hipStream_t s, const char *what)
+{
+    *dst = nullptr;
+    if (count == 0) return CWT_OK;
+    hipError_t e = hipMalloc((void **)dst, count * sizeof(T));
+    if (e != hipSuccess) {
+        *dst = nullptr;
+        return fail(CWT_E_NOMEM, "hipMalloc(%s, %zu bytes) failed: %s", what, count * sizeof(T),
+                    hipGetErrorName(e));
+    }
+    if (src) {
+        e = hipMemcpyAsync(*dst, src, count * sizeof(T), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        // src is owned by the plan and outlives the copy.
+    }
+    return CWT_OK;
+}
+
+void free_plan_device(cwt_plan &P)
+{
+    void *ptrs[] = {P.d_freqs, P.d_sigmas, P.d_band, P.d_H, P.d_tw, P.d_grp_freq, P.d_grp_off};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    P.d_freqs = P.d_sigmas = nullptr;
+    P.d_band = nullptr;
+    P.d_H = nullptr;
+    P.d_tw = nullptr;
+    P.d_grp_freq = P.d_grp_off = nullptr;
+}
+
+int upload_plan(cwt_plan &P, hipStream_t s)
+{
+    int rc;
+    if ((rc = dev_upload(&P.d_freqs, P.freqs.data(), P.freqs.size(), s, "freqs"))) return rc;
+    if ((rc = dev_upload(&P.d_sigmas, P.sigmas.data(), P.sigmas.size(), s, "sigmas"))) return rc;
+    if ((rc = dev_upload(&P.d_band, P.bands.data(), P.bands.size(), s, "bands"))) return rc;
+    if ((rc = dev_upload<float>(&P.d_H, nullptr, std::max<int64_t>(P.total_bins, 1), s, "H")))
+        return rc;
+    if ((rc = dev_upload<float2>(&P.d_tw, nullptr, P.L, s, "twiddles"))) return rc;
+    if (P.n_bands > 0) {
+        if ((rc = dev_upload(&P.d_grp_freq, P.grp_freq.data(), P.grp_freq.size(), s, "groups")))
+            return rc;
+        if ((rc = dev_upload(&P.d_grp_off, P.grp_off.data(), P.grp_off.size(), s, "group offs")))
+            return rc;
+    }
+    GenParams g{};
+    g.sfreq = P.sfreq;
+    g.L = P.L;
+    g.F = P.F;
+    g.wavelet = P.opts.wavelet;
+    g.freqs = P.d_freqs;
+    g.sigmas = P.d_sigmas;
+    g.band = P.d_band;
+    g.H = P.d_H;
+    g.tw = P.d_tw;
+    hipError_t e = launch_generate(g, P.max_bins, s);
+    if (e != hipSuccess) return hip_fail(e, "generator launch");
+    return CWT_OK;
+}
+
+size_t workspace_bytes(const cwt_plan &P, int64_t C)
+{
+    const int64_t Lh = P.L / 2 + 1;
+    size_t b = (size_t)C * (size_t)Lh * sizeof(float2);
+    return (b + 255) & ~(size_t)255;
+}
+
+int enqueue_execute(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride, void *out,
+                    void *ws, hipStream_t s)
+{
+    if (C == 0) return CWT_OK;
+    float2 *Xh = reinterpret_cast<float2 *>(ws);
+    FwdParams fp{};
+    fp.x = x;
+    fp.C = (int)C;
+    fp.N = (int)P.n;
+    fp.x_stride = x_stride;
+    fp.Xh = Xh;
+    fp.Lh = P.L / 2 + 1;
+    fp.tw = P.d_tw;
+    fp.rp = P.rp;
+    hipError_t e = launch_forward(fp, s);
+    if (e != hipSuccess) return hip_fail(e, "forward FFT launch");
+    MainParams mp{};
+    mp.Xh = Xh;
+    mp.Lh = P.L / 2 + 1;
+    mp.H = P.d_H;
+    mp.band = P.d_band;
+    mp.tw = P.d_tw;
+    mp.out = out;
+    mp.out_mode = P.opts.out;
+    mp.N = (int)P.n;
+    mp.F = P.F;
+    mp.C = (int)C;
+    mp.n_rows = (P.opts.out == CWT_OUT_BANDPOWER_F32) ? P.n_bands : P.F;
+    mp.grp_freq = P.d_grp_freq;
+    mp.grp_off = P.d_grp_off;
+    mp.rp = P.rp;
+    e = launch_main(mp, s);
+    if (e != hipSuccess) return hip_fail(e, "transform launch");
+    return CWT_OK;
+}
+
+}  // namespace cwtrt
+
+extern "C" int cwt_plan_create(cwt_plan **out, int64_t n, double sfreq, const double *freqs,
+                               int32_t n_freqs, const double *n_cycles, double omega0,
+                               const cwt_plan_opts *opts, void *stream)
+{
+    clear_error();
+    if (!out) return fail(CWT_E_INVALID, "cwt_plan_create: out is NULL");
+    *out = nullptr;
+    cwt_plan *P = new (std::nothrow) cwt_plan();
+    if (!P) return fail(CWT_E_NOMEM, "host allocation of the plan failed");
+    int rc = validate_and_plan(*P, n, sfreq, freqs, n_freqs, n_cycles, omega0, opts);
+    if (rc == CWT_OK && P->opts.precision != CWT_PREC_FP32 && !split_precision_available())
+        rc = fail(CWT_E_UNSUPPORTED, "split-precision MFMA path is not available in this build");
+    if (rc == CWT_OK) rc = check_device(&P->device);
+    if (rc == CWT_OK) rc = upload_plan(*P, (hipStream_t)stream);
+    if (rc == CWT_OK && P->opts.precision != CWT_PREC_FP32)
+        rc = prepare_split_precision(*P, (hipStream_t)stream);
+    if (rc != CWT_OK) {
+        free_plan_device(*P);
+        delete P;
+        return rc;
+    }
+    *out = P;
+    return CWT_OK;
+}
+
+static void fill_desc(const cwt_plan *P, cwt_plan_desc *d)
+{
+    std::memset(d, 0, sizeof *d);
+    d->n = P->n;
+    d->L = P->L;
+    d->n_freqs = P->F;
+    d->n_bands = P->n_bands;
+    d->out = P->opts.out;
+    d->precision = P->opts.precision;
+    d->wavelet = P->opts.wavelet;
+    d->threads = P->rp.threads;
+    d->n_passes = P->rp.n_pass;
+    for (int i = 0; i < P->rp.n_pass && i < 16; ++i) d->radix[i] = P->rp.radix[i];
+    d->out_rows = (P->opts.out == CWT_OUT_BANDPOWER_F32) ? P->n_bands : P->F;
+    d->out_elem_bytes = (P->opts.out == CWT_OUT_COMPLEX64) ? 8 : 4;
+    d->spectrum_bins = P->total_bins;
+    d->max_band_bins = P->max_bins;
+}
+
+extern "C" int cwt_plan_info(const cwt_plan *P, cwt_plan_desc *d)
+{
+    if (!P || !d) return fail(CWT_E_INVALID, "cwt_plan_info: NULL argument");
+    fill_desc(P, d);
+    return CWT_OK;
+}
+
+extern "C" int cwt_plan_describe(cwt_plan_desc *d, int64_t n, double sfreq, const double *freqs,
+                                 int32_t n_freqs, const double *n_cycles, double omega0,
+                                 const cwt_plan_opts *opts)
+{
+    clear_error();
+    if (!d) return fail(CWT_E_INVALID, "cwt_plan_describe: desc is NULL");
+    cwt_plan P;
+    int rc = validate_and_plan(P, n, sfreq, freqs, n_freqs, n_cycles, omega0, opts);
+    if (rc != CWT_OK) return rc;
+    fill_desc(&P, d);
+    return CWT_OK;
+}
+
+extern "C" int cwt_plan_band_of_freq(const cwt_plan *P, int32_t *bof)
+{
+    if (!P || !bof) return fail(CWT_E_INVALID, "cwt_plan_band_of_freq: NULL argument");
+    for (int i = 0; i < P->F; ++i) bof[i] = P->band_of_freq[i];
+    return CWT_OK;
+}
+
+extern "C" size_t cwt_workspace_size(const cwt_plan *P, int64_t C)
+{
+    if (!P || C < 0) return 0;
+    return workspace_bytes(*P, C) + split_workspace_bytes(*P, C);
+}
+
+extern "C" int cwt_execute(const cwt_plan *P, const float *x, int64_t C, void *out, void *ws,
+                           size_t ws_bytes, void *stream)
+{
+    clear_error();
+    if (!P) return fail(CWT_E_INVALID, "cwt_execute: plan is NULL");
+    if (C < 0 || C > (int64_t)1 << 24) return fail(CWT_E_INVALID, "C out of range");
+    if (C == 0) return CWT_OK;
+    if (!x || !out || !ws) return fail(CWT_E_INVALID, "cwt_execute: NULL device pointer");
+    if (((uintptr_t)ws & 255) != 0) return fail(CWT_E_INVALID, "ws must be 256-byte aligned");
+    if (((uintptr_t)x & 3) != 0 || ((uintptr_t)out & 7) != 0)
+        return fail(CWT_E_INVALID, "x must be 4-byte and out 8-byte aligned");
+    const size_t need = cwt_workspace_size(P, C);
+    if (ws_bytes < need)
+        return fail(CWT_E_INVALID, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    const int64_t rows = (P->opts.out == CWT_OUT_BANDPOWER_F32) ? P->n_bands : P->F;
+    if (C * rows > (int64_t)INT32_MAX)
+        return fail(CWT_E_UNSUPPORTED, "C x rows exceeds the grid limit");
+    if (P->opts.precision != CWT_PREC_FP32)
+        return enqueue_execute_split(*P, x, C, P->n, out, ws, (hipStream_t)stream);
+    return enqueue_execute(*P, x, C, P->n, out, ws, (hipStream_t)stream);
+}
+
+extern "C" int cwt_plan_copy_tables(const cwt_plan *P, float *H_host, int32_t *band_host,
+                                    float *tw_host, void *stream)
+{
+    if (!P) return fail(CWT_E_INVALID, "cwt_plan_copy_tables: plan is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (H_host && P->total_bins > 0) {
+        e = hipMemcpyAsync(H_host, P->d_H, P->total_bins * sizeof(float), hipMemcpyDeviceToHost,
+                           s);
+        if (e != hipSuccess) return hip_fail(e, "copy H");
+    }
+    if (tw_host) {
+        e = hipMemcpyAsync(tw_host, P->d_tw, (size_t)P->L * sizeof(float2),
+                           hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return hip_fail(e, "copy twiddles");
+    }
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (band_host)
+        for (int i = 0; i < P->F; ++i) {
+            band_host[3 * i] = P->bands[i].lo;
+            band_host[3 * i + 1] = P->bands[i].K;
+            band_host[3 * i + 2] = P->bands[i].off;
+        }
+    return CWT_OK;
+}
+
+extern "C" int cwt_plan_destroy(cwt_plan *P, void *stream)
+{
+    if (!P) return CWT_OK;
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    release_split_precision(*P);
+    free_plan_device(*P);
+    delete P;
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize in cwt_plan_destroy");
+    return CWT_OK;
+}

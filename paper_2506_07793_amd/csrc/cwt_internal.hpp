@@ -1,0 +1,66 @@
+// Host-side plan object and internal entry points of libcwt.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/cwt.h"
+#include "cwt_kernels.hpp"
+
+struct cwt_split_state;  // split-precision (MFMA) tables, when built
+
+struct cwt_plan {
+    int64_t n = 0;
+    double sfreq = 0;
+    int L = 0;
+    int F = 0;
+    int n_bands = 0;
+    int device = 0;
+    cwt_plan_opts opts{};
+    cwtk::RadixPlan rp{};
+    std::vector<double> freqs, sigmas, band_edges;
+    std::vector<cwtk::BandDesc> bands;
+    std::vector<int> grp_freq, grp_off, band_of_freq;
+    int total_bins = 0;
+    int max_bins = 0;
+    // device tables
+    double *d_freqs = nullptr;
+    double *d_sigmas = nullptr;
+    cwtk::BandDesc *d_band = nullptr;
+    float *d_H = nullptr;
+    float2 *d_tw = nullptr;
+    int *d_grp_freq = nullptr;
+    int *d_grp_off = nullptr;
+    cwt_split_state *split = nullptr;
+};
+
+namespace cwtrt {
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+void clear_error();
+
+int64_t pad_length(int64_t n, int mode, int64_t explicit_len);
+bool make_radix_plan(int L, cwtk::RadixPlan &rp);
+cwtk::BandDesc spectrum_band(int L, double sfreq, double f, double sigma, int wavelet);
+int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
+                      int32_t n_freqs, const double *n_cycles, double omega0,
+                      const cwt_plan_opts *opts);
+int check_device(int *dev_out);
+int upload_plan(cwt_plan &P, hipStream_t s);
+void free_plan_device(cwt_plan &P);
+size_t workspace_bytes(const cwt_plan &P, int64_t C);
+int enqueue_execute(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride, void *out,
+                    void *ws, hipStream_t s);
+
+// split-precision MFMA path
+bool split_precision_available();
+int prepare_split_precision(cwt_plan &P, hipStream_t s);
+void release_split_precision(cwt_plan &P);
+size_t split_workspace_bytes(const cwt_plan &P, int64_t C);
+int enqueue_execute_split(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride,
+                          void *out, void *ws, hipStream_t s);
+
+}  // namespace cwtrt

@@ -1,0 +1,247 @@
+// HIP kernels of the plain FP32 CWT path for gfx950.
+//
+//   k_generate : FP64 wavelet spectra (Morlet / Gabor Fourier-domain
+//                equations, evaluated at s * omega_b) and the FP64 twiddle
+//                table, each rounded once to FP32.
+//   k_forward  : forward real FFT of two channels per workgroup (packed as
+//                one complex transform), half spectra to the workspace.
+//   k_main     : per (channel, frequency) or (channel, band): spectral
+//                multiply over the stored band of the wavelet spectrum ->
+//                LDS-resident inverse Stockham FFT -> crop to n samples ->
+//                complex64 / |W|^2 / band-mean store, natural order.
+#include "cwt_kernels.hpp"
+#include "fft_core.hpp"
+
+namespace cwtk {
+
+// ------------------------------------------------------------ generators --
+
+__global__ void k_generate(GenParams p)
+{
+    const int f = blockIdx.y;
+    if (f < p.F) {
+        const BandDesc bd = p.band[f];
+        const int k = blockIdx.x * blockDim.x + threadIdx.x;
+        if (k >= bd.K) return;
+        const double PI = 3.14159265358979323846;
+        const double sigma = p.sigmas[f];
+        const double s = sigma / (2.0 * PI * p.freqs[f]);
+        double kappa = 0.0, c = 1.0;
+        if (p.wavelet == 0) {
+            kappa = exp(-0.5 * sigma * sigma);
+            c = 1.0 / sqrt(1.0 + exp(-sigma * sigma) - 2.0 * exp(-0.75 * sigma * sigma));
+        }
+        const int bt = bd.lo + k;  // signed bin
+        const double u = s * (2.0 * PI * p.sfreq * (double)bt / (double)p.L);
+        const double du = sigma - u;
+        const double psi = c * pow(PI, -0.25) * (exp(-0.5 * du * du) - kappa * exp(-0.5 * u * u));
+        const double h = sqrt(2.0 * PI * s * p.sfreq) * psi / (double)p.L;
+        p.H[bd.off + k] = (float)h;
+    } else {
+        // twiddles exp(+2 pi i m / L)
+        for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < p.L; m += gridDim.x * blockDim.x) {
+            double sn, cs;
+            sincospi(2.0 * (double)m / (double)p.L, &sn, &cs);
+            p.tw[m] = make_float2((float)cs, (float)sn);
+        }
+    }
+}
+
+hipError_t launch_generate(const GenParams &p, int max_bins, hipStream_t s)
+{
+    int bx = (max_bins + 255) / 256;
+    int bt = (p.L + 255) / 256;
+    if (bt > bx) bx = bt;
+    if (bx < 1) bx = 1;
+    hipLaunchKernelGGL(k_generate, dim3(bx, p.F + 1), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------- forward FFT --
+
+template <int MAXV>
+__global__ void __launch_bounds__(1024) k_forward(FwdParams p)
+{
+    extern __shared__ cf lds[];
+    const int L = p.rp.L, T = blockDim.x, tid = threadIdx.x;
+    const int c0 = 2 * blockIdx.x;
+    const bool has1 = (c0 + 1) < p.C;
+    const float *x0 = p.x + (int64_t)c0 * p.x_stride;
+    const float *x1 = p.x + (int64_t)(c0 + 1) * p.x_stride;
+    const cf *tw = reinterpret_cast<const cf *>(p.tw);
+    const int N = p.N;
+
+    auto lds_load = [](int idx) -> cf { return lds[idx]; };
+    auto lds_store = [](int, int idx, cf v) { lds[idx] = v; };
+    auto in_load = [=](int idx) -> cf {
+        cf z = mk(0.f, 0.f);
+        if (idx < N) {
+            z.x = x0[idx];
+            if (has1) z.y = x1[idx];
+        }
+        return z;
+    };
+
+    int Ns = 1;
+    for (int i = 0; i < p.rp.n_pass; ++i) {
+        const int R = p.rp.radix[i];
+        if (i == 0)
+            stockham_pass_rt<-1, MAXV, true>(R, L, Ns, T, tid, tw, in_load, lds_store);
+        else
+            stockham_pass_rt<-1, MAXV, true>(R, L, Ns, T, tid, tw, lds_load, lds_store);
+        __syncthreads();
+        Ns *= R;
+    }
+    // Separate the two real channels: X0 = (Z[b] + conj Z[-b]) / 2,
+    // X1 = (Z[b] - conj Z[-b]) / (2 i).
+    float2 *X0 = p.Xh + (int64_t)c0 * p.Lh;
+    float2 *X1 = X0 + p.Lh;
+    for (int b = tid; b < p.Lh; b += T) {
+        const cf z = lds[b];
+        const int nb = (b == 0) ? 0 : L - b;
+        const cf zc = mk(lds[nb].x, -lds[nb].y);
+        const cf s = add(z, zc), d = sub(z, zc);
+        X0[b] = make_float2(0.5f * s.x, 0.5f * s.y);
+        if (has1) X1[b] = make_float2(0.5f * d.y, -0.5f * d.x);
+    }
+}
+
+static void set_lds_limit(const void *fn, size_t bytes)
+{
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_forward(const FwdParams &p, hipStream_t s)
+{
+    const int blocks = (p.C + 1) / 2;
+    const size_t lds = (size_t)p.rp.L * sizeof(cf);
+    if (p.rp.maxv <= 16) {
+        set_lds_limit((const void *)k_forward<16>, lds);
+        hipLaunchKernelGGL(k_forward<16>, dim3(blocks), dim3(p.rp.threads), lds, s, p);
+    } else {
+        set_lds_limit((const void *)k_forward<24>, lds);
+        hipLaunchKernelGGL(k_forward<24>, dim3(blocks), dim3(p.rp.threads), lds, s, p);
+    }
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------- main kernel --
+
+template <int MAXV, int MODE>
+__global__ void __launch_bounds__(1024) k_main(MainParams p)
+{
+    extern __shared__ cf lds[];
+    const int L = p.rp.L, T = blockDim.x, tid = threadIdx.x;
+    const int N = p.N, Lh = p.Lh;
+    const int n_pass = p.rp.n_pass;
+    const cf *tw = reinterpret_cast<const cf *>(p.tw);
+
+    const int c = blockIdx.x / p.n_rows;
+    const int row = blockIdx.x - c * p.n_rows;
+    int qb, qe;
+    if (MODE == kOutBand) {
+        qb = p.grp_off[row];
+        qe = p.grp_off[row + 1];
+    } else {
+        qb = row;
+        qe = row + 1;
+    }
+    const cf *X = reinterpret_cast<const cf *>(p.Xh) + (int64_t)c * Lh;
+
+    float *orow_band = reinterpret_cast<float *>(p.out) + ((int64_t)c * p.n_rows + row) * N;
+    const float inv_n = 1.0f / (float)(qe - qb);
+
+    auto lds_load = [](int idx) -> cf { return lds[idx]; };
+    auto lds_store = [](int, int idx, cf v) { lds[idx] = v; };
+
+    for (int q = qb; q < qe; ++q) {
+        const int f = (MODE == kOutBand) ? p.grp_freq[q] : q;
+        const BandDesc bd = p.band[f];
+        const float *Hf = p.H + bd.off;
+        const int lo = bd.lo, K = bd.K;
+        auto spec_load = [=](int b) -> cf {
+            int off = b - lo;
+            if (off < 0) off += L;
+            if (off >= L) off -= L;
+            cf y = mk(0.f, 0.f);
+            if (off < K) {
+                const float h = Hf[off];
+                cf xv;
+                if (b < Lh) {
+                    xv = X[b];
+                } else {
+                    xv = X[L - b];
+                    xv.y = -xv.y;
+                }
+                y = scale(xv, h);
+            }
+            return y;
+        };
+        float2 *ocx = reinterpret_cast<float2 *>(p.out) + ((int64_t)c * p.n_rows + f) * N;
+        float *opw = reinterpret_cast<float *>(p.out) + ((int64_t)c * p.n_rows + f) * N;
+        // Band mode accumulates in the output row, which only this
+        // workgroup touches; every thread revisits the same samples t for
+        // each frequency, so it reads back its own earlier writes.
+        const bool first = (q == qb), final_f = (q == qe - 1);
+        auto epi = [=](int, int t, cf v) {
+            if (t < N) {
+                const float pw = v.x * v.x + v.y * v.y;
+                if (MODE == kOutComplex) {
+                    ocx[t] = make_float2(v.x, v.y);
+                } else if (MODE == kOutPower) {
+                    opw[t] = pw;
+                } else {
+                    float a = first ? pw : orow_band[t] + pw;
+                    orow_band[t] = final_f ? a * inv_n : a;
+                }
+            }
+        };
+
+        int Ns = 1;
+        for (int i = 0; i < n_pass; ++i) {
+            const int R = p.rp.radix[i];
+            const bool last = (i == n_pass - 1);
+            if (!last) {
+                if (i == 0)
+                    stockham_pass_rt<1, MAXV, true>(R, L, Ns, T, tid, tw, spec_load, lds_store);
+                else
+                    stockham_pass_rt<1, MAXV, true>(R, L, Ns, T, tid, tw, lds_load, lds_store);
+                __syncthreads();
+            } else {
+                if (i == 0)
+                    stockham_pass_rt<1, MAXV, false>(R, L, Ns, T, tid, tw, spec_load, epi);
+                else
+                    stockham_pass_rt<1, MAXV, true>(R, L, Ns, T, tid, tw, lds_load, epi);
+            }
+            Ns *= R;
+        }
+    }
+}
+
+template <int MAXV, int MODE>
+static hipError_t launch_main_t(const MainParams &p, hipStream_t s)
+{
+    const int blocks = p.C * p.n_rows;
+    const size_t lds = (size_t)p.rp.L * sizeof(cf);
+    set_lds_limit((const void *)k_main<MAXV, MODE>, lds);
+    hipLaunchKernelGGL((k_main<MAXV, MODE>), dim3(blocks), dim3(p.rp.threads), lds, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_main(const MainParams &p, hipStream_t s)
+{
+    if (p.rp.maxv <= 16) {
+        switch (p.out_mode) {
+        case kOutComplex: return launch_main_t<16, kOutComplex>(p, s);
+        case kOutPower: return launch_main_t<16, kOutPower>(p, s);
+        default: return launch_main_t<16, kOutBand>(p, s);
+        }
+    }
+    switch (p.out_mode) {
+    case kOutComplex: return launch_main_t<24, kOutComplex>(p, s);
+    case kOutPower: return launch_main_t<24, kOutPower>(p, s);
+    default: return launch_main_t<24, kOutBand>(p, s);
+    }
+}
+
+}  // namespace cwtk

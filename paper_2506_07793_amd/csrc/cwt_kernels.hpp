@@ -1,0 +1,75 @@
+// Kernel launch interface shared by the host runtime of libcwt.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cwtk {
+
+constexpr int kMaxPasses = 16;
+
+// Radix schedule of one padded length: the passes of the Stockham FFT and
+// the workgroup size that runs them.
+struct RadixPlan {
+    int L;
+    int n_pass;
+    int radix[kMaxPasses];
+    int threads;
+    int maxv;  // most complex values one thread holds in a pass (16 or 24)
+};
+
+// Per-frequency stored spectrum band: signed first bin, bin count, offset.
+struct BandDesc {
+    int lo;
+    int K;
+    int off;
+    int pad_;
+};
+
+// Forward real FFT of C channels, two per workgroup: Xh[c][b], b <= L/2.
+struct FwdParams {
+    const float *x;   // [C][N]
+    int C, N;
+    int64_t x_stride; // elements between channels
+    float2 *Xh;       // [C][Lh]
+    int Lh;
+    const float2 *tw; // [L]
+    RadixPlan rp;
+};
+
+enum OutMode { kOutComplex = 0, kOutPower = 1, kOutBand = 2 };
+
+// Fused spectral multiply -> inverse FFT -> crop -> epilogue.
+struct MainParams {
+    const float2 *Xh;      // [C][Lh] half spectra
+    int Lh;
+    const float *H;        // packed wavelet spectra (1/L folded in)
+    const BandDesc *band;  // [F]
+    const float2 *tw;      // [L]
+    void *out;
+    int out_mode;
+    int N, F, C;
+    int n_rows;            // rows per channel in the output (F or n_bands)
+    const int *grp_freq;   // band mode: frequency indices, band after band
+    const int *grp_off;    // band mode: [n_bands + 1] offsets into grp_freq
+    RadixPlan rp;
+};
+
+// FP64 generators (run once per plan).
+struct GenParams {
+    double sfreq;
+    int L;
+    int F;
+    int wavelet;           // 0 Morlet, 1 Gabor
+    const double *freqs;   // [F] device
+    const double *sigmas;  // [F] device
+    const BandDesc *band;  // [F] device
+    float *H;              // packed output
+    float2 *tw;            // [L]
+};
+
+hipError_t launch_generate(const GenParams &p, int total_bins, hipStream_t s);
+hipError_t launch_forward(const FwdParams &p, hipStream_t s);
+hipError_t launch_main(const MainParams &p, hipStream_t s);
+
+}  // namespace cwtk

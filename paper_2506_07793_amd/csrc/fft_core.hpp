@@ -1,0 +1,291 @@
+// Device building blocks of the LDS-resident mixed-radix FFT (gfx950, wave64).
+//
+// The transform is a Stockham autosort FFT: pass p with radix R and
+// Ns = product of the radices of the earlier passes reads element
+// j + r * (L / R) of butterfly j (r < R), multiplies it by the twiddle
+// exp(SIGN 2 pi i (j mod Ns) r / (Ns R)), takes an R-point DFT and writes
+// element r to (j div Ns) Ns R + (j mod Ns) + r Ns.  After the last pass the
+// data is in natural order, so the last pass can store straight to global
+// memory with consecutive threads on consecutive outputs.
+//
+// SIGN = +1 is the inverse direction exp(+2 pi i k t / L) (no 1/L here; the
+// caller folds it into the wavelet spectrum), SIGN = -1 the forward one.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cwtk {
+
+struct cf {
+    float x, y;
+};
+
+__device__ __forceinline__ cf mk(float a, float b) { return cf{a, b}; }
+__device__ __forceinline__ cf add(cf a, cf b) { return cf{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cf sub(cf a, cf b) { return cf{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ cf mul(cf a, cf b)
+{
+    return cf{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ cf scale(cf a, float s) { return cf{a.x * s, a.y * s}; }
+// multiply by SIGN * i
+template <int SIGN>
+__device__ __forceinline__ cf mul_si(cf a)
+{
+    return SIGN > 0 ? cf{-a.y, a.x} : cf{a.y, -a.x};
+}
+template <int SIGN>
+__device__ __forceinline__ cf conj_if(cf w)
+{
+    return SIGN > 0 ? w : cf{w.x, -w.y};
+}
+
+// ---------------------------------------------------------------- codelets --
+// V[k] = sum_r v[r] exp(SIGN 2 pi i r k / R), natural order in and out.
+
+template <int R, int SIGN>
+struct Dft;
+
+template <int SIGN>
+struct Dft<1, SIGN> {  // length-1 transform (L == 1)
+    static __device__ __forceinline__ void run(cf *) {}
+};
+
+template <int SIGN>
+struct Dft<2, SIGN> {
+    static __device__ __forceinline__ void run(cf *v)
+    {
+        cf a = v[0], b = v[1];
+        v[0] = add(a, b);
+        v[1] = sub(a, b);
+    }
+};
+
+template <int SIGN>
+struct Dft<4, SIGN> {
+    static __device__ __forceinline__ void run(cf *v)
+    {
+        cf s02 = add(v[0], v[2]), d02 = sub(v[0], v[2]);
+        cf s13 = add(v[1], v[3]), d13 = mul_si<SIGN>(sub(v[1], v[3]));
+        v[0] = add(s02, s13);
+        v[2] = sub(s02, s13);
+        v[1] = add(d02, d13);
+        v[3] = sub(d02, d13);
+    }
+};
+
+template <int SIGN>
+struct Dft<8, SIGN> {
+    static __device__ __forceinline__ void run(cf *v)
+    {
+        const float h = 0.70710678118654752440f;
+        cf e[4] = {v[0], v[2], v[4], v[6]};
+        cf o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<4, SIGN>::run(e);
+        Dft<4, SIGN>::run(o);
+        // o[k] *= exp(SIGN 2 pi i k / 8)
+        cf o1 = o[1], o3 = o[3];
+        o[1] = scale(add(o1, mul_si<SIGN>(o1)), h);          // (1 + s i)/sqrt2
+        o[2] = mul_si<SIGN>(o[2]);                           // s i
+        o[3] = scale(sub(mul_si<SIGN>(o3), o3), h);          // (-1 + s i)/sqrt2
+        for (int k = 0; k < 4; ++k) {
+            v[k] = add(e[k], o[k]);
+            v[k + 4] = sub(e[k], o[k]);
+        }
+    }
+};
+
+template <int SIGN>
+struct Dft<16, SIGN> {
+    // 16 = 4 x 4: DFT4 over r1 for each r2, twiddle exp(SIGN 2 pi i r2 k1 / 16),
+    // DFT4 over r2 for each k1; output index k1 + 4 k2.
+    static __device__ __forceinline__ void run(cf *v)
+    {
+        const float c1 = 0.92387953251128675613f;  // cos(pi/8)
+        const float s1 = 0.38268343236508977173f;  // sin(pi/8)
+        const float h = 0.70710678118654752440f;
+        cf a[4][4];
+#pragma unroll
+        for (int r2 = 0; r2 < 4; ++r2) {
+            cf t[4] = {v[r2], v[4 + r2], v[8 + r2], v[12 + r2]};
+            Dft<4, SIGN>::run(t);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) a[r2][k1] = t[k1];
+        }
+        const float sg = (float)SIGN;
+        // r2 = 1: k1 = 1, 2, 3 -> angles pi/8, pi/4, 3pi/8
+        a[1][1] = mul(a[1][1], mk(c1, sg * s1));
+        a[1][2] = mul(a[1][2], mk(h, sg * h));
+        a[1][3] = mul(a[1][3], mk(s1, sg * c1));
+        // r2 = 2: angles pi/4, pi/2, 3pi/4
+        a[2][1] = mul(a[2][1], mk(h, sg * h));
+        a[2][2] = mul_si<SIGN>(a[2][2]);
+        a[2][3] = mul(a[2][3], mk(-h, sg * h));
+        // r2 = 3: angles 3pi/8, 3pi/4, 9pi/8
+        a[3][1] = mul(a[3][1], mk(s1, sg * c1));
+        a[3][2] = mul(a[3][2], mk(-h, sg * h));
+        a[3][3] = mul(a[3][3], mk(-c1, -sg * s1));
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            cf t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+            Dft<4, SIGN>::run(t);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+        }
+    }
+};
+
+// Odd prime radices: V_k = a0 + sum_m cos(2 pi m k / R)(a_m + a_{R-m})
+//                          + SIGN i sum_m sin(2 pi m k / R)(a_m - a_{R-m}).
+template <int R>
+struct OddConst;
+template <>
+struct OddConst<3> {
+    static constexpr float c[1][1] = {{-0.5f}};
+    static constexpr float s[1][1] = {{0.86602540378443864676f}};
+};
+template <>
+struct OddConst<5> {
+    // [k-1][m-1] for k, m in 1..2
+    static constexpr float c[2][2] = {{0.30901699437494742410f, -0.80901699437494742410f},
+                                      {-0.80901699437494742410f, 0.30901699437494742410f}};
+    static constexpr float s[2][2] = {{0.95105651629515357212f, 0.58778525229247312917f},
+                                      {0.58778525229247312917f, -0.95105651629515357212f}};
+};
+template <>
+struct OddConst<7> {
+    static constexpr float c[3][3] = {
+        {0.62348980185873353053f, -0.22252093395631440429f, -0.90096886790241912624f},
+        {-0.22252093395631440429f, -0.90096886790241912624f, 0.62348980185873353053f},
+        {-0.90096886790241912624f, 0.62348980185873353053f, -0.22252093395631440429f}};
+    static constexpr float s[3][3] = {
+        {0.78183148246802980871f, 0.97492791218182360702f, 0.43388373911755812048f},
+        {0.97492791218182360702f, -0.43388373911755812048f, -0.78183148246802980871f},
+        {0.43388373911755812048f, -0.78183148246802980871f, 0.97492791218182360702f}};
+};
+
+template <int R, int SIGN>
+struct DftOdd {
+    static __device__ __forceinline__ void run(cf *v)
+    {
+        constexpr int H = (R - 1) / 2;
+        cf sp[H], dm[H];
+#pragma unroll
+        for (int m = 1; m <= H; ++m) {
+            sp[m - 1] = add(v[m], v[R - m]);
+            dm[m - 1] = sub(v[m], v[R - m]);
+        }
+        cf a0 = v[0];
+        cf sum = a0;
+#pragma unroll
+        for (int m = 0; m < H; ++m) sum = add(sum, sp[m]);
+        v[0] = sum;
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+            cf re = a0, im = mk(0.f, 0.f);
+#pragma unroll
+            for (int m = 1; m <= H; ++m) {
+                const float cc = OddConst<R>::c[k - 1][m - 1];
+                const float ss = OddConst<R>::s[k - 1][m - 1];
+                re = add(re, scale(sp[m - 1], cc));
+                im = add(im, scale(dm[m - 1], ss));
+            }
+            cf sim = mul_si<SIGN>(im);
+            v[k] = add(re, sim);
+            v[R - k] = sub(re, sim);
+        }
+    }
+};
+template <int SIGN>
+struct Dft<3, SIGN> : DftOdd<3, SIGN> {};
+template <int SIGN>
+struct Dft<5, SIGN> : DftOdd<5, SIGN> {};
+template <int SIGN>
+struct Dft<7, SIGN> : DftOdd<7, SIGN> {};
+
+// Butterflies a thread may hold at once in one pass when it holds at most
+// MAXV complex values.
+template <int R, int MAXV>
+struct MaxB {
+    static constexpr int value = (MAXV / R) > 0 ? (MAXV / R) : 1;
+};
+
+// ------------------------------------------------------------- twiddles --
+// w[r] = w1^r for r < R by balanced products (depth ceil(log2 r)), so the
+// rounding error stays within a few FP32 ulps of the table value w1.
+template <int R>
+__device__ __forceinline__ void twiddle_powers(cf w1, cf *w)
+{
+    w[0] = mk(1.f, 0.f);
+    if (R > 1) w[1] = w1;
+#pragma unroll
+    for (int r = 2; r < R; ++r) w[r] = mul(w[r / 2], w[r - r / 2]);
+}
+
+// --------------------------------------------------------------- one pass --
+// Generic pass over the L/R butterflies of a workgroup of T threads; thread
+// `tid` owns butterflies j = tid + k T.  `load(idx)` supplies input element
+// idx, `store(slot, idx, value)` receives output element idx, where
+// slot = k R + r numbers the values this thread holds.  When SYNC_MID is set
+// a workgroup barrier separates all loads from all stores (in-place LDS use).
+// Twiddles derive from tw[m] = exp(+2 pi i m / L) (conjugated for SIGN < 0).
+// The pass is a separate (not inlined) function so that a kernel holding
+// every radix keeps one pass's registers live at a time.
+template <int R, int SIGN, int MAXV, bool SYNC_MID, class Load, class Store>
+__device__ __attribute__((noinline)) void stockham_pass(int L, int Ns, int T, int tid,
+                                                        const cf *__restrict__ tw, Load load,
+                                                        Store store)
+{
+    constexpr int MB = MaxB<R, MAXV>::value;
+    const int S = L / R;
+    const int twstep = L / (Ns * R);
+    cf v[MB][R];
+#pragma unroll
+    for (int k = 0; k < MB; ++k) {
+        const int j = tid + k * T;
+        if (j < S) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[k][r] = load(j + r * S);
+        }
+    }
+    if (SYNC_MID) __syncthreads();
+#pragma unroll
+    for (int k = 0; k < MB; ++k) {
+        const int j = tid + k * T;
+        if (j < S) {
+            const int jm = j % Ns;
+            if (Ns > 1) {
+                cf w[R];
+                twiddle_powers<R>(conj_if<SIGN>(tw[(unsigned)(jm * twstep)]), w);
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[k][r] = mul(v[k][r], w[r]);
+            }
+            Dft<R, SIGN>::run(v[k]);
+            const int base = (j - jm) * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r) store(k * R + r, base + r * Ns, v[k][r]);
+        }
+    }
+}
+
+// Dispatch one pass of runtime radix R to its compiled form.
+template <int SIGN, int MAXV, bool SYNC_MID, class Load, class Store>
+__device__ __forceinline__ void stockham_pass_rt(int R, int L, int Ns, int T, int tid,
+                                                 const cf *__restrict__ tw, Load load,
+                                                 Store store)
+{
+    switch (R) {
+    case 16: stockham_pass<16, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
+    case 8: stockham_pass<8, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
+    case 4: stockham_pass<4, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
+    case 2: stockham_pass<2, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
+    case 3: stockham_pass<3, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
+    case 5: stockham_pass<5, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
+    case 7: stockham_pass<7, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
+    case 1: stockham_pass<1, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
+    default: break;
+    }
+}
+
+}  // namespace cwtk

@@ -1,0 +1,239 @@
+"""GPU parity of the plain FP32 path against the FP64 oracle (through the C ABI).
+
+Gate (the workload's stated tolerance): e_P = max|P_gpu - P_orc| / max P_orc
+<= 1e-5 per recording, with P = |W|^2; e_W = max|dW| / max|W| is reported.
+The oracle gets the same float32 input samples promoted to float64.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2506_07793_amd as cwt
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_P = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _run(x32, sfreq, freqs, cyc, **kw):
+    plan = cwt.Plan(x32.shape[-1], sfreq, freqs, n_cycles=cyc, **kw)
+    out = plan.execute(torch.from_numpy(np.ascontiguousarray(x32)).cuda())
+    torch.cuda.synchronize()
+    return plan, out.cpu().numpy()
+
+
+def _parity(Wg, Wr, label):
+    e_P, e_W = oracle.parity_errors(Wg, Wr)
+    print("%s: e_P=%.3e e_W=%.3e" % (label, e_P, e_W), flush=True)
+    assert e_P <= TOL_P, "%s: e_P=%g" % (label, e_P)
+    return e_P, e_W
+
+
+# ------------------------------------------------------------------ tables --
+
+@pytest.mark.parametrize("n,sfreq,F,wavelet", [(4096, 1000.0, 100, "morlet"), (1000, 1000.0, 50, "morlet"),
+                                              (2000, 1000.0, 40, "gabor"), (4116, 2048.0, 30, "morlet")])
+def test_tables_within_one_ulp_of_fp64(n, sfreq, F, wavelet):
+    """FP64 GPU generators: each stored spectrum bin (1/L folded in) and each
+    twiddle is within one FP32 ulp of the FP64 value."""
+    freqs = synth.log_freqs(1.0, min(100.0, 0.45 * sfreq), F)
+    cyc = synth.eeg_cycles(freqs)
+    plan = cwt.Plan(n, sfreq, freqs, n_cycles=cyc, wavelet=wavelet)
+    H, band, tw = plan.tables()
+    L = plan.L
+    kind = oracle.GABOR if wavelet == "gabor" else oracle.MORLET
+    for i, (f, s) in enumerate(zip(freqs, cyc)):
+        lo, K, off = band[i]
+        Hf = oracle.wavelet_spectrum(L, sfreq, f, s, kind) / L
+        idx = (lo + np.arange(K)) % L
+        ref = Hf[idx]
+        got = H[off:off + K].astype(np.float64)
+        ulp = np.spacing(np.abs(ref).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(got - ref) <= ulp + 1e-45), (i, np.max(np.abs(got - ref) / ulp))
+        # bins outside the stored band are below 1e-12 of the peak
+        mask = np.ones(L, bool)
+        mask[idx] = False
+        assert np.all(np.abs(Hf[mask]) <= 1e-12 * np.abs(Hf).max())
+    m = np.arange(L)
+    ref = np.exp(2j * np.pi * m / L)
+    d = np.abs(tw.astype(np.complex128) - ref)
+    assert np.max(d) <= 1.2e-7
+    plan.close()
+
+
+# ------------------------------------------------------------ config 0 --
+
+@pytest.mark.parametrize("pad,L", [("smooth7", 1000), ("pow2", 1024)])
+def test_config0_single_channel(pad, L):
+    """1 ch x 1000 samples at 1000 Hz, Morlet sigma 7, 50 freqs 1-50 Hz."""
+    x = synth.config0_signal().astype(np.float32)
+    freqs = np.arange(1.0, 51.0)
+    plan, W = _run(x, 1000.0, freqs, 7.0, pad=pad)
+    assert plan.L == L
+    ref = oracle.cwt(x.astype(np.float64), 1000.0, freqs, 7.0, L=L)
+    _parity(W, ref, "config0 " + pad)
+    plan.close()
+
+
+# ------------------------------------------------------------ config 1 --
+
+def _config1(C):
+    d = synth.config1(C=C)
+    return d["x"], d["sfreq"], d["freqs"], d["n_cycles"]
+
+
+def test_config1_full_oracle_two_channels():
+    x, sfreq, freqs, cyc = _config1(2)
+    plan, W = _run(x, sfreq, freqs, cyc)
+    ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc)
+    _parity(W, ref, "config1 C=2 full")
+    # per-row worst (each (c, f) row relative to its own peak power)
+    Pg, Pr = oracle.power(W), oracle.power(ref)
+    row = np.max(np.abs(Pg - Pr), axis=2) / np.max(Pr, axis=2)
+    print("worst per-row e_P %.3e" % row.max())
+    assert row.max() <= 1e-4
+    plan.close()
+
+
+def test_config1_full_size_sampled_rows():
+    """64 ch x 4096 x 100 freqs (the benchmarked shape), oracle on sampled rows."""
+    x, sfreq, freqs, cyc = _config1(64)
+    plan, W = _run(x, sfreq, freqs, cyc)
+    assert W.shape == (64, 100, 4096)
+    rng = np.random.default_rng(11)
+    rows = np.stack([rng.integers(0, 64, 24), rng.integers(0, 100, 24)], axis=1)
+    rows[0] = (0, 0)
+    rows[1] = (63, 99)
+    ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc, rows=rows)
+    got = W[rows[:, 0], rows[:, 1]]
+    _parity(got, ref, "config1 64ch sampled")
+    plan.close()
+
+
+def test_config1_power_and_bandpower():
+    x, sfreq, freqs, cyc = _config1(3)
+    ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc)
+    Pr = oracle.power(ref)
+    plan, P = _run(x, sfreq, freqs, cyc, out="power")
+    assert P.dtype == np.float32
+    e = np.max(np.abs(P - Pr)) / Pr.max()
+    print("power e_P %.3e" % e)
+    assert e <= TOL_P
+    plan.close()
+    plan, BP = _run(x, sfreq, freqs, cyc, out="bandpower")
+    g = oracle.band_groups(freqs)
+    BPr = oracle.band_power(Pr, g)
+    assert BP.shape == BPr.shape == (3, 5, 4096)
+    for b in range(5):
+        e = np.max(np.abs(BP[:, b] - BPr[:, b])) / BPr[:, b].max()
+        print("band %d e=%.3e" % (b, e))
+        assert e <= TOL_P
+    assert np.array_equal(plan.band_of_freq(),
+                          np.concatenate([np.full(len(gi), i) for i, gi in enumerate(g)]))
+    plan.close()
+
+
+# ------------------------------------------------------- shapes and edges --
+
+@pytest.mark.parametrize("C,N,sfreq,pad,expl", [
+    (3, 105, 250.0, "none", 0),        # odd L = 3*5*7
+    (1, 4097, 1000.0, "smooth7", 0),   # ragged: L = 4116 = 4*3*7^3
+    (2, 777, 500.0, "smooth7", 0),     # L = 784 = 16*7^2
+    (5, 300, 300.0, "explicit", 512),
+    (1, 1, 100.0, "smooth7", 0),       # L = 1
+    (2, 2, 100.0, "smooth7", 0),
+    (1, 16384, 2048.0, "smooth7", 0),
+    (4, 999, 1000.0, "smooth7", 0),    # L = 1000 with a 1-sample crop
+])
+def test_shapes_and_edges(C, N, sfreq, pad, expl):
+    rng = np.random.default_rng(N)
+    x = rng.normal(0, 20, size=(C, N)).astype(np.float32)
+    freqs = synth.log_freqs(max(0.5, sfreq / 400), 0.45 * sfreq, 12)
+    cyc = synth.eeg_cycles(freqs)
+    plan, W = _run(x, sfreq, freqs, cyc, pad=pad, explicit_len=expl)
+    if C * N * plan.L * 12 <= 3e9:
+        ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc, L=plan.L)
+        Wg = W
+    else:
+        rows = [(c, f) for c in range(C) for f in (0, 5, 11)]
+        ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc, L=plan.L, rows=rows)
+        Wg = np.stack([W[c, f] for c, f in rows])
+    _parity(Wg, ref, "C=%d N=%d L=%d radices=%s" % (C, N, plan.L, plan.radices))
+    plan.close()
+
+
+def test_max_length_20000_sampled():
+    """Largest supported padded length (160 KB of LDS), oracle on sampled rows."""
+    x = synth.eeg(2, 20000, 2048.0, seed=3)
+    freqs = synth.log_freqs(0.5, 200.0, 30)
+    cyc = synth.eeg_cycles(freqs)
+    plan, W = _run(x, 2048.0, freqs, cyc)
+    assert plan.L == 20000
+    rows = [(0, 0), (1, 14), (0, 29), (1, 3)]
+    ref = oracle.cwt(x.astype(np.float64), 2048.0, freqs, cyc, rows=rows)
+    _parity(np.stack([W[c, f] for c, f in rows]), ref, "L=20000 radices=%s" % plan.radices)
+    plan.close()
+
+
+def test_gabor_and_near_nyquist():
+    """Gabor (kappa = 0) and a small-sigma frequency whose spectrum reaches Nyquist."""
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(2, 640)).astype(np.float32)
+    freqs = np.array([3.0, 40.0, 110.0, 124.0])
+    cyc = np.array([3.0, 6.0, 2.0, 1.5])
+    for wavelet in ("morlet", "gabor"):
+        plan, W = _run(x, 250.0, freqs, cyc, wavelet=wavelet)
+        kind = oracle.GABOR if wavelet == "gabor" else oracle.MORLET
+        ref = oracle.cwt(x.astype(np.float64), 250.0, freqs, cyc, kind=kind)
+        _parity(W, ref, wavelet + " near Nyquist")
+        plan.close()
+
+
+def test_zero_channels_is_noop_and_determinism():
+    x, sfreq, freqs, cyc = _config1(4)
+    plan = cwt.Plan(4096, sfreq, freqs, n_cycles=cyc)
+    xt = torch.from_numpy(x).cuda()
+    out = plan.alloc_output(4)
+    ws = plan.alloc_workspace(4)
+    from paper_2506_07793_amd import _lib
+    lib = _lib.load()
+    import ctypes
+    rc = lib.cwt_execute(plan.handle, ctypes.c_void_p(xt.data_ptr()), 0,
+                         ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                         ws.numel(), None)
+    assert rc == 0
+    a = plan.execute(xt).cpu()
+    b = plan.execute(xt).cpu()
+    assert torch.equal(a, b), "two runs differ bitwise"
+    # workspace too small is rejected before launch
+    rc = lib.cwt_execute(plan.handle, ctypes.c_void_p(xt.data_ptr()), 4,
+                         ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), 16, None)
+    assert rc == _lib.CWT_E_INVALID
+    plan.close()
+
+
+def test_two_streams_concurrently():
+    x, sfreq, freqs, cyc = _config1(8)
+    plan = cwt.Plan(4096, sfreq, freqs, n_cycles=cyc, out="power")
+    xt = torch.from_numpy(x).cuda()
+    ref = plan.execute(xt).clone()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    o1 = plan.alloc_output(8)
+    o2 = plan.alloc_output(8)
+    w1, w2 = plan.alloc_workspace(8), plan.alloc_workspace(8)
+    plan.execute(xt, out=o1, ws=w1, stream=s1)
+    plan.execute(xt, out=o2, ws=w2, stream=s2)
+    torch.cuda.synchronize()
+    assert torch.equal(o1, ref) and torch.equal(o2, ref)
+    plan.close()
