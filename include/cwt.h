@@ -154,6 +154,21 @@ int cwt_execute(const cwt_plan *plan, const float *x, int64_t C, void *out, void
                 size_t ws_bytes, void *stream);
 
 /*
+ * The two stages of cwt_execute, for callers that reuse the channel spectra
+ * or time the stages separately.  cwt_forward_spectra writes the half
+ * spectra X[c][b] = sum_{k<n} x[c][k] exp(-2 pi i b k / L), b <= L/2, of the
+ * zero-padded channels into ws (section "Fourier transformed formula": the
+ * FFT of the signal).  cwt_transform_spectra reads them from ws and writes
+ * out exactly as cwt_execute does (multiply by the wavelet spectra, inverse
+ * FFT, crop, output mode).  Same arguments, validation and workspace as
+ * cwt_execute; cwt_transform_spectra takes no x.
+ */
+int cwt_forward_spectra(const cwt_plan *plan, const float *x, int64_t C, void *ws,
+                        size_t ws_bytes, void *stream);
+int cwt_transform_spectra(const cwt_plan *plan, int64_t C, void *out, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/*
  * Copy the plan's tables to host memory for inspection (synchronises
  * `stream`).  H_host receives spectrum_bins floats (the stored bins of every
  * frequency, frequency after frequency); band_host receives 3 ints per

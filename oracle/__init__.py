@@ -251,6 +251,10 @@ def parity_errors(W_test, W_ref):
     """e_P = max|P_t - P_r| / max P_r and e_W = max|W_t - W_r| / max|W_r| (FP64)."""
     W_test = np.asarray(W_test).astype(np.complex128)
     P_t, P_r = power(W_test), power(W_ref)
-    e_P = float(np.max(np.abs(P_t - P_r)) / np.max(P_r))
-    e_W = float(np.max(np.abs(W_test - W_ref)) / np.max(np.abs(W_ref)))
+    # An all-zero reference (e.g. a Morlet transform of a constant) is
+    # compared in absolute terms.
+    dP = float(np.max(np.abs(P_t - P_r)))
+    dW = float(np.max(np.abs(W_test - W_ref)))
+    e_P = dP / float(np.max(P_r)) if np.max(P_r) > 0 else dP
+    e_W = dW / float(np.max(np.abs(W_ref))) if np.max(np.abs(W_ref)) > 0 else dW
     return e_P, e_W

@@ -167,6 +167,19 @@ class Plan:
                                          ws.numel() * ws.element_size(), _stream_handle(stream)))
         return out
 
+    def forward_spectra(self, x, ws, stream=None):
+        """Stage 1 of execute: channel half spectra into ws (cwt_forward_spectra)."""
+        C = int(x.shape[0])
+        _lib.check(self._lib.cwt_forward_spectra(self._ptr, _dptr(x), C, _dptr(ws),
+                                                 ws.numel() * ws.element_size(),
+                                                 _stream_handle(stream)))
+
+    def transform_spectra(self, C, out, ws, stream=None):
+        """Stage 2 of execute: spectra in ws -> out (cwt_transform_spectra)."""
+        _lib.check(self._lib.cwt_transform_spectra(self._ptr, int(C), _dptr(out), _dptr(ws),
+                                                   ws.numel() * ws.element_size(),
+                                                   _stream_handle(stream)))
+
     def close(self, stream=None):
         if getattr(self, "_ptr", None):
             try:

@@ -85,6 +85,8 @@ SIGNATURES = {
     "cwt_plan_band_of_freq": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32)]),
     "cwt_workspace_size": (_SZ, [_VP, _I64]),
     "cwt_execute": (ctypes.c_int, [_VP, _VP, _I64, _VP, _VP, _SZ, _VP]),
+    "cwt_forward_spectra": (ctypes.c_int, [_VP, _VP, _I64, _VP, _SZ, _VP]),
+    "cwt_transform_spectra": (ctypes.c_int, [_VP, _I64, _VP, _VP, _SZ, _VP]),
     "cwt_plan_copy_tables": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float),
                                             ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_float), _VP]),

@@ -369,24 +369,29 @@ size_t workspace_bytes(const cwt_plan &P, int64_t C)
     return (b + 255) & ~(size_t)255;
 }
 
-int enqueue_execute(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride, void *out,
-                    void *ws, hipStream_t s)
+int enqueue_forward(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride, void *ws,
+                    hipStream_t s)
 {
     if (C == 0) return CWT_OK;
-    float2 *Xh = reinterpret_cast<float2 *>(ws);
     FwdParams fp{};
     fp.x = x;
     fp.C = (int)C;
     fp.N = (int)P.n;
     fp.x_stride = x_stride;
-    fp.Xh = Xh;
+    fp.Xh = reinterpret_cast<float2 *>(ws);
     fp.Lh = P.L / 2 + 1;
     fp.tw = P.d_tw;
     fp.rp = P.rp;
     hipError_t e = launch_forward(fp, s);
     if (e != hipSuccess) return hip_fail(e, "forward FFT launch");
+    return CWT_OK;
+}
+
+int enqueue_transform(const cwt_plan &P, int64_t C, void *out, void *ws, hipStream_t s)
+{
+    if (C == 0) return CWT_OK;
     MainParams mp{};
-    mp.Xh = Xh;
+    mp.Xh = reinterpret_cast<const float2 *>(ws);
     mp.Lh = P.L / 2 + 1;
     mp.H = P.d_H;
     mp.band = P.d_band;
@@ -400,9 +405,17 @@ int enqueue_execute(const cwt_plan &P, const float *x, int64_t C, int64_t x_stri
     mp.grp_freq = P.d_grp_freq;
     mp.grp_off = P.d_grp_off;
     mp.rp = P.rp;
-    e = launch_main(mp, s);
+    hipError_t e = launch_main(mp, s);
     if (e != hipSuccess) return hip_fail(e, "transform launch");
     return CWT_OK;
+}
+
+int enqueue_execute(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride, void *out,
+                    void *ws, hipStream_t s)
+{
+    int rc = enqueue_forward(P, x, C, x_stride, ws, s);
+    if (rc != CWT_OK) return rc;
+    return enqueue_transform(P, C, out, ws, s);
 }
 
 }  // namespace cwtrt
@@ -484,16 +497,18 @@ extern "C" size_t cwt_workspace_size(const cwt_plan *P, int64_t C)
     return workspace_bytes(*P, C) + split_workspace_bytes(*P, C);
 }
 
-extern "C" int cwt_execute(const cwt_plan *P, const float *x, int64_t C, void *out, void *ws,
-                           size_t ws_bytes, void *stream)
+// Validation shared by cwt_execute and its two stages.  x_needed / out_needed
+// say which device pointers the call uses.
+static int check_exec_args(const cwt_plan *P, const float *x, bool x_needed, int64_t C,
+                           void *out, bool out_needed, void *ws, size_t ws_bytes)
 {
-    clear_error();
-    if (!P) return fail(CWT_E_INVALID, "cwt_execute: plan is NULL");
+    if (!P) return fail(CWT_E_INVALID, "plan is NULL");
     if (C < 0 || C > (int64_t)1 << 24) return fail(CWT_E_INVALID, "C out of range");
     if (C == 0) return CWT_OK;
-    if (!x || !out || !ws) return fail(CWT_E_INVALID, "cwt_execute: NULL device pointer");
+    if ((x_needed && !x) || (out_needed && !out) || !ws)
+        return fail(CWT_E_INVALID, "NULL device pointer");
     if (((uintptr_t)ws & 255) != 0) return fail(CWT_E_INVALID, "ws must be 256-byte aligned");
-    if (((uintptr_t)x & 3) != 0 || ((uintptr_t)out & 7) != 0)
+    if ((x_needed && ((uintptr_t)x & 3) != 0) || (out_needed && ((uintptr_t)out & 7) != 0))
         return fail(CWT_E_INVALID, "x must be 4-byte and out 8-byte aligned");
     const size_t need = cwt_workspace_size(P, C);
     if (ws_bytes < need)
@@ -501,9 +516,38 @@ extern "C" int cwt_execute(const cwt_plan *P, const float *x, int64_t C, void *o
     const int64_t rows = (P->opts.out == CWT_OUT_BANDPOWER_F32) ? P->n_bands : P->F;
     if (C * rows > (int64_t)INT32_MAX)
         return fail(CWT_E_UNSUPPORTED, "C x rows exceeds the grid limit");
+    return CWT_OK;
+}
+
+extern "C" int cwt_execute(const cwt_plan *P, const float *x, int64_t C, void *out, void *ws,
+                           size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_exec_args(P, x, true, C, out, true, ws, ws_bytes);
+    if (rc != CWT_OK || C == 0) return rc;
     if (P->opts.precision != CWT_PREC_FP32)
         return enqueue_execute_split(*P, x, C, P->n, out, ws, (hipStream_t)stream);
     return enqueue_execute(*P, x, C, P->n, out, ws, (hipStream_t)stream);
+}
+
+extern "C" int cwt_forward_spectra(const cwt_plan *P, const float *x, int64_t C, void *ws,
+                                   size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_exec_args(P, x, true, C, nullptr, false, ws, ws_bytes);
+    if (rc != CWT_OK || C == 0) return rc;
+    return enqueue_forward(*P, x, C, P->n, ws, (hipStream_t)stream);
+}
+
+extern "C" int cwt_transform_spectra(const cwt_plan *P, int64_t C, void *out, void *ws,
+                                     size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = check_exec_args(P, nullptr, false, C, out, true, ws, ws_bytes);
+    if (rc != CWT_OK || C == 0) return rc;
+    if (P->opts.precision != CWT_PREC_FP32)
+        return enqueue_transform_split(*P, C, out, ws, (hipStream_t)stream);
+    return enqueue_transform(*P, C, out, ws, (hipStream_t)stream);
 }
 
 extern "C" int cwt_plan_copy_tables(const cwt_plan *P, float *H_host, int32_t *band_host,

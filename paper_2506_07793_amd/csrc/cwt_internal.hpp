@@ -52,6 +52,9 @@ int check_device(int *dev_out);
 int upload_plan(cwt_plan &P, hipStream_t s);
 void free_plan_device(cwt_plan &P);
 size_t workspace_bytes(const cwt_plan &P, int64_t C);
+int enqueue_forward(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride, void *ws,
+                    hipStream_t s);
+int enqueue_transform(const cwt_plan &P, int64_t C, void *out, void *ws, hipStream_t s);
 int enqueue_execute(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride, void *out,
                     void *ws, hipStream_t s);
 
@@ -62,5 +65,6 @@ void release_split_precision(cwt_plan &P);
 size_t split_workspace_bytes(const cwt_plan &P, int64_t C);
 int enqueue_execute_split(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride,
                           void *out, void *ws, hipStream_t s);
+int enqueue_transform_split(const cwt_plan &P, int64_t C, void *out, void *ws, hipStream_t s);
 
 }  // namespace cwtrt

@@ -13,5 +13,9 @@ int enqueue_execute_split(const cwt_plan &, const float *, int64_t, int64_t, voi
 {
     return CWT_E_UNSUPPORTED;
 }
+int enqueue_transform_split(const cwt_plan &, int64_t, void *, void *, hipStream_t)
+{
+    return CWT_E_UNSUPPORTED;
+}
 
 }  // namespace cwtrt

@@ -150,8 +150,8 @@ def test_config1_power_and_bandpower():
     (1, 4097, 1000.0, "smooth7", 0),   # ragged: L = 4116 = 4*3*7^3
     (2, 777, 500.0, "smooth7", 0),     # L = 784 = 16*7^2
     (5, 300, 300.0, "explicit", 512),
-    (1, 1, 100.0, "smooth7", 0),       # L = 1
-    (2, 2, 100.0, "smooth7", 0),
+    (1, 1, 100.0, "smooth7", 0),       # L = 1 (Morlet: exactly zero output)
+    (2, 3, 100.0, "smooth7", 0),       # L = 3
     (1, 16384, 2048.0, "smooth7", 0),
     (4, 999, 1000.0, "smooth7", 0),    # L = 1000 with a 1-sample crop
 ])
@@ -169,6 +169,34 @@ def test_shapes_and_edges(C, N, sfreq, pad, expl):
         ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc, L=plan.L, rows=rows)
         Wg = np.stack([W[c, f] for c, f in rows])
     _parity(Wg, ref, "C=%d N=%d L=%d radices=%s" % (C, N, plan.L, plan.radices))
+    plan.close()
+
+
+@pytest.mark.parametrize("n", [1, 2])
+def test_tiny_lengths_gabor(n):
+    """N = L = 1 and 2 with Gabor (non-zero at zero frequency)."""
+    x = np.array([[3.5, -1.25][:n]], dtype=np.float32)
+    freqs = np.array([10.0, 40.0])
+    cyc = np.array([2.0, 2.0])
+    plan, W = _run(x, 100.0, freqs, cyc, wavelet="gabor")
+    ref = oracle.cwt(x.astype(np.float64), 100.0, freqs, cyc, kind="gabor")
+    assert np.abs(ref).max() > 1e-3
+    _parity(W, ref, "N=%d gabor" % n)
+    plan.close()
+
+
+def test_stages_equal_execute():
+    """cwt_forward_spectra + cwt_transform_spectra == cwt_execute, bitwise."""
+    x, sfreq, freqs, cyc = _config1(5)
+    plan = cwt.Plan(4096, sfreq, freqs, n_cycles=cyc)
+    xt = torch.from_numpy(x).cuda()
+    a = plan.execute(xt)
+    ws = plan.alloc_workspace(5)
+    b = plan.alloc_output(5)
+    plan.forward_spectra(xt, ws)
+    plan.transform_spectra(5, b, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
     plan.close()
 
 
