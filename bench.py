@@ -34,8 +34,13 @@ def parse():
     ap.add_argument("--out", default="complex64", choices=["complex64", "power"])
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing (profiling runs)")
-    ap.add_argument("--cpu-channels", type=int, default=32,
+    ap.add_argument("--cpu-channels", type=int, default=64,
                     help="channels of the oracle's timed sample (all 100 frequencies each)")
+    ap.add_argument("--graph", type=int, default=0,
+                    help="1: replay the step as a captured HIP graph; 0: direct launches (default)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (scales the HBM "
+                         "byte counters of a profiler run)")
     return ap.parse_args()
 
 
@@ -54,47 +59,65 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        a = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4, "copies": 3}), flush=True)
+        return
     C, N, F = 64, 4096, 100
     cfg = synth.config1(seed=2, C=C, N=N, F=F)
     x = torch.from_numpy(cfg["x"]).to(dev)
     plan = cwt.Plan(N, cfg["sfreq"], cfg["freqs"], n_cycles=cfg["n_cycles"], out=args.out)
     out = plan.alloc_output(C, device=dev)
     ws = plan.alloc_workspace(C, device=dev)
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()  # default priority
 
     def step():
         plan.forward_spectra(x, ws, stream=stream)
         plan.transform_spectra(C, out, ws, stream=stream)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
     K = args.steps
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    mids = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-            for _ in range(K)]
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for i in range(K):
-        plan.forward_spectra(x, ws, stream=stream)
-        mids[i][0].record(stream)
-        plan.transform_spectra(C, out, ws, stream=stream)
-        mids[i][1].record(stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms_step = ev0.elapsed_time(ev1) / K
-    ms_main = sum(a.elapsed_time(b) for a, b in mids) / K
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
 
-    # Same loop without the inner markers: the plain step time.
-    ev0.record(stream)
-    for _ in range(K):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms_step_plain = ev0.elapsed_time(ev1) / K
-    ms_step = min(ms_step, ms_step_plain)
+        # 1) direct launches, with events around the transform kernel of every
+        #    step: its average duration on the stream it runs on
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        mids = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for _ in range(K)]
+        ev0.record(stream)
+        for i in range(K):
+            plan.forward_spectra(x, ws, stream=stream)
+            mids[i][0].record(stream)
+            plan.transform_spectra(C, out, ws, stream=stream)
+            mids[i][1].record(stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_main = sum(a.elapsed_time(b) for a, b in mids) / K
+
+        # 2) the timed region: K steps, as a replayed HIP graph or direct launches
+        if args.graph:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=stream):
+                step()
+            for _ in range(args.warmup):
+                g.replay()
+            run = g.replay
+        else:
+            run = step
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(K):
+            run()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_step = ev0.elapsed_time(ev1) / K
 
     pts = C * F * N
     value = pts / (ms_step * 1e-3)
@@ -125,7 +148,8 @@ def main():
         "config": {"workload": "plain CWT 64ch x 4096 @1000Hz, 100 log freqs 1-100 Hz, "
                                "n_cycles=clip(f/2,3,10), FP32 in, %s out" % args.out,
                    "channels": C, "samples": N, "freqs": F, "padded_len": plan.L,
-                   "radices": plan.radices, "out": args.out},
+                   "radices": plan.radices, "out": args.out,
+                   "launch": "hip graph replay" if args.graph else "direct"},
         "roofline": {"bound": "hbm", "kernel": "k_main (multiply + inverse FFT + store)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

@@ -119,6 +119,9 @@ typedef struct cwt_plan_desc {
     int64_t out_elem_bytes;  /* 8 (complex64) or 4 (float32)                     */
     int64_t spectrum_bins;   /* total stored wavelet-spectrum bins (all freqs)   */
     int64_t max_band_bins;   /* widest stored spectrum band                      */
+    int32_t kernel;          /* 0 generic runtime-radix kernel, 1 register-resident
+                                kernel specialised for this padded length          */
+    int32_t reserved_;
 } cwt_plan_desc;
 
 int cwt_plan_info(const cwt_plan *plan, cwt_plan_desc *desc);

@@ -60,6 +60,8 @@ class PlanDesc(ctypes.Structure):
         ("out_elem_bytes", ctypes.c_int64),
         ("spectrum_bins", ctypes.c_int64),
         ("max_band_bins", ctypes.c_int64),
+        ("kernel", ctypes.c_int32),
+        ("reserved_", ctypes.c_int32),
     ]
 
 

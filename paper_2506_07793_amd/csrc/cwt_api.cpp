@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -283,6 +284,12 @@ int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
     }
     P.total_bins = off;
     P.max_bins = maxK;
+    // Register-resident kernels serve the lengths that have one, unless the
+    // environment variable CWT_GENERIC_ONLY=1 asks for the generic kernel.
+    const char *gen = std::getenv("CWT_GENERIC_ONLY");
+    P.use_fixed = fixed_main_available(P.L) && !(gen && gen[0] == '1');
+    const char *var = std::getenv("CWT_FIXED_VARIANT");
+    P.variant = var ? std::atoi(var) : 1;
     return CWT_OK;
 }
 
@@ -382,7 +389,7 @@ int enqueue_forward(const cwt_plan &P, const float *x, int64_t C, int64_t x_stri
     fp.Lh = P.L / 2 + 1;
     fp.tw = P.d_tw;
     fp.rp = P.rp;
-    hipError_t e = launch_forward(fp, s);
+    hipError_t e = P.use_fixed ? launch_forward_fixed(fp, s) : launch_forward(fp, s);
     if (e != hipSuccess) return hip_fail(e, "forward FFT launch");
     return CWT_OK;
 }
@@ -405,7 +412,8 @@ int enqueue_transform(const cwt_plan &P, int64_t C, void *out, void *ws, hipStre
     mp.grp_freq = P.d_grp_freq;
     mp.grp_off = P.d_grp_off;
     mp.rp = P.rp;
-    hipError_t e = launch_main(mp, s);
+    mp.variant = P.variant;
+    hipError_t e = (P.use_fixed) ? launch_main_fixed(mp, s) : launch_main(mp, s);
     if (e != hipSuccess) return hip_fail(e, "transform launch");
     return CWT_OK;
 }
@@ -462,6 +470,7 @@ static void fill_desc(const cwt_plan *P, cwt_plan_desc *d)
     d->out_elem_bytes = (P->opts.out == CWT_OUT_COMPLEX64) ? 8 : 4;
     d->spectrum_bins = P->total_bins;
     d->max_band_bins = P->max_bins;
+    d->kernel = P->use_fixed ? 1 : 0;
 }
 
 extern "C" int cwt_plan_info(const cwt_plan *P, cwt_plan_desc *d)

@@ -25,6 +25,8 @@ struct cwt_plan {
     std::vector<int> grp_freq, grp_off, band_of_freq;
     int total_bins = 0;
     int max_bins = 0;
+    bool use_fixed = false;  // register-resident kernel for this length
+    int variant = 0;         // its twiddle method (0 table, 1 powers)
     // device tables
     double *d_freqs = nullptr;
     double *d_sigmas = nullptr;

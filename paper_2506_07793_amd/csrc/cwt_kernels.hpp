@@ -53,6 +53,7 @@ struct MainParams {
     const int *grp_freq;   // band mode: frequency indices, band after band
     const int *grp_off;    // band mode: [n_bands + 1] offsets into grp_freq
     RadixPlan rp;
+    int variant;           // register-resident kernel: 0 table twiddles, 1 power twiddles
 };
 
 // FP64 generators (run once per plan).
@@ -71,5 +72,9 @@ struct GenParams {
 hipError_t launch_generate(const GenParams &p, int total_bins, hipStream_t s);
 hipError_t launch_forward(const FwdParams &p, hipStream_t s);
 hipError_t launch_main(const MainParams &p, hipStream_t s);
+// Register-resident kernels for the padded lengths that have one.
+bool fixed_main_available(int L);
+hipError_t launch_main_fixed(const MainParams &p, hipStream_t s);
+hipError_t launch_forward_fixed(const FwdParams &p, hipStream_t s);
 
 }  // namespace cwtk

@@ -17,7 +17,9 @@
 
 namespace cwtk {
 
-struct cf {
+// 8-byte aligned so that LDS and global accesses are single 64-bit operations
+// (ds_read_b64 / global_load_dwordx2) rather than pairs of 32-bit ones.
+struct alignas(8) cf {
     float x, y;
 };
 

@@ -154,6 +154,10 @@ def test_config1_power_and_bandpower():
     (2, 3, 100.0, "smooth7", 0),       # L = 3
     (1, 16384, 2048.0, "smooth7", 0),
     (4, 999, 1000.0, "smooth7", 0),    # L = 1000 with a 1-sample crop
+    (3, 1000, 1000.0, "pow2", 0),      # L = 1024 register-resident kernel
+    (2, 2000, 1000.0, "pow2", 0),      # L = 2048 register-resident kernel
+    (1, 7000, 2048.0, "pow2", 0),      # L = 8192 register-resident kernel
+    (65, 4096, 1000.0, "smooth7", 0),  # odd channel count, L = 4096
 ])
 def test_shapes_and_edges(C, N, sfreq, pad, expl):
     rng = np.random.default_rng(N)
@@ -168,7 +172,8 @@ def test_shapes_and_edges(C, N, sfreq, pad, expl):
         rows = [(c, f) for c in range(C) for f in (0, 5, 11)]
         ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc, L=plan.L, rows=rows)
         Wg = np.stack([W[c, f] for c, f in rows])
-    _parity(Wg, ref, "C=%d N=%d L=%d radices=%s" % (C, N, plan.L, plan.radices))
+    _parity(Wg, ref, "C=%d N=%d L=%d radices=%s kernel=%d" % (C, N, plan.L, plan.radices,
+                                                              plan.desc.kernel))
     plan.close()
 
 
@@ -265,3 +270,32 @@ def test_two_streams_concurrently():
     torch.cuda.synchronize()
     assert torch.equal(o1, ref) and torch.equal(o2, ref)
     plan.close()
+
+
+@pytest.mark.parametrize("out", ["complex64", "power", "bandpower"])
+def test_fixed_and_generic_kernels_agree(out, monkeypatch):
+    """The register-resident kernel (L = 4096) and the generic kernel both
+    match the oracle, and each other to FP32 rounding."""
+    x, sfreq, freqs, cyc = _config1(2)
+    xt = torch.from_numpy(x).cuda()
+    monkeypatch.setenv("CWT_GENERIC_ONLY", "1")
+    pg = cwt.Plan(4096, sfreq, freqs, n_cycles=cyc, out=out)
+    monkeypatch.delenv("CWT_GENERIC_ONLY")
+    pf = cwt.Plan(4096, sfreq, freqs, n_cycles=cyc, out=out)
+    assert pg.desc.kernel == 0 and pf.desc.kernel == 1
+    a = pg.execute(xt).cpu().numpy()
+    b = pf.execute(xt).cpu().numpy()
+    ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc)
+    if out == "complex64":
+        _parity(a, ref, "generic")
+        _parity(b, ref, "fixed")
+    else:
+        Pr = oracle.power(ref)
+        if out == "bandpower":
+            Pr = oracle.band_power(Pr, oracle.band_groups(freqs))
+        for name, got in (("generic", a), ("fixed", b)):
+            e = np.max(np.abs(got - Pr)) / Pr.max()
+            print("%s %s e=%.3e" % (out, name, e))
+            assert e <= TOL_P
+    pg.close()
+    pf.close()
