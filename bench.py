@@ -119,6 +119,17 @@ def main():
         torch.cuda.synchronize()
         ms_step = ev0.elapsed_time(ev1) / K
 
+        # Store ceiling: a plain device fill of the same output buffer.
+        fill = out.view(torch.float32)
+        for _ in range(3):
+            fill.fill_(0.0)
+        ev0.record(stream)
+        for _ in range(K):
+            fill.fill_(0.0)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_fill = ev0.elapsed_time(ev1) / K
+
     pts = C * F * N
     value = pts / (ms_step * 1e-3)
     desc = plan.desc
@@ -155,6 +166,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes": main_bytes, "avg_ms": ms_main},
         "step_hbm_frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "store_ceiling": {"kernel": "torch fill_ of the output buffer",
+                          "GBps": out.numel() * out.element_size() / (ms_fill * 1e-3) / 1e9,
+                          "ms": ms_fill},
     }
 
     if not args.no_cpu_baseline:

@@ -28,15 +28,12 @@ namespace {
 constexpr int kV = 16;  // values per thread
 typedef float f2v __attribute__((ext_vector_type(2)));
 
-// Slot of element i: the low five bits are XORed with a function of the
-// higher bits, so that 32 consecutive lanes hit 32 distinct 8-byte slots
-// (modulo 32) for every access pattern below: unit-stride column reads
-// t + T m, the radix-16 scatter 16 t + r, and the second-pass scatters.
-__device__ __forceinline__ int sw(int i)
-{
-    const int x = i >> 5;
-    return i ^ (((x & 15) ^ (((x >> 3) & 15) << 1) ^ (((x >> 3) & 1) << 4)) & 31);
-}
+// Slot of element i: the low four bits are XORed with bits 4-7 and 8-11.  On
+// gfx950 a 64-bit LDS read is conflict-free when the slots of each 32-lane
+// group differ modulo 32, a 64-bit write when those of each 16-lane group
+// differ modulo 16; with this map the unit-stride column reads t + T m, the
+// radix-16 scatter 16 t + r and both second-pass scatters satisfy that.
+__device__ __forceinline__ int sw(int i) { return i ^ (((i >> 4) ^ (i >> 8)) & 15); }
 
 // w[r] = exp(SIGN 2 pi i base r / L) for 0 < r < R, from the table.
 template <int R, int SIGN>
