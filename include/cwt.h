@@ -181,6 +181,82 @@ int cwt_transform_spectra(const cwt_plan *plan, int64_t C, void *out, void *ws,
 int cwt_plan_copy_tables(const cwt_plan *plan, float *H_host, int32_t *band_host,
                          float *tw_host, void *stream);
 
+/* ---- streaming ------------------------------------------------------- */
+/*
+ * Real-time form (the paper's real-time EEG use, sections "Introduction" and
+ * "Discussion"): sessions push samples, and for every completed hop the
+ * server transforms the sliding window of the last n samples (the plan's n)
+ * and reports, per channel and band, the band power averaged over the hop's
+ * trailing samples of the window's transform.  A worker thread batches the
+ * hops of many sessions into one set of launches (up to max_batch sessions,
+ * launched when the oldest pending hop has waited deadline_us or the batch
+ * is full) and stamps the completion time of each result.
+ */
+typedef struct cwt_server cwt_server;
+typedef struct cwt_session cwt_session;
+
+typedef struct cwt_server_opts {
+    int32_t max_batch;        /* sessions per launch (default 256)                   */
+    int32_t deadline_us;      /* longest wait of a pending hop before launch (1000)  */
+    int32_t max_pending;      /* queued hops per session before CWT_E_AGAIN (64)     */
+    int32_t reserved_;
+} cwt_server_opts;
+
+typedef struct cwt_server_stats {
+    uint64_t batches;         /* launches so far                                   */
+    uint64_t hops;            /* hops processed (emitting or not)                  */
+    uint64_t results;         /* band-power results delivered                      */
+    uint64_t rejected;        /* pushes refused with CWT_E_AGAIN                   */
+    uint64_t sessions_open;
+    uint64_t hbm_bytes_used;  /* device bytes held by rings and batch workspaces   */
+    uint64_t hbm_budget_bytes;
+} cwt_server_stats;
+
+int cwt_server_opts_init(cwt_server_opts *opts);
+
+/* Create a server that may hold at most hbm_budget_bytes of device memory
+ * for session rings and batch workspaces.  It owns a non-blocking HIP stream
+ * of default priority and a worker thread.  opts may be NULL (defaults). */
+int cwt_server_create(cwt_server **out, size_t hbm_budget_bytes, const cwt_server_opts *opts);
+
+/* Stop the worker (pending hops are processed first), free everything.
+ * Sessions still open are closed. */
+int cwt_server_destroy(cwt_server *srv);
+
+/* Open a session of C channels on `plan` (which must use CWT_OUT_BANDPOWER_F32;
+ * its n is the window length W) with hop samples per result, 1 <= hop <= W.
+ * The ring holds zeros until the first W samples have arrived; no result is
+ * produced before that.  Returns CWT_E_BUDGET when the session's ring plus
+ * (for a new (plan, C, hop) class) the class's batch workspace would exceed
+ * the server's budget.  The plan must outlive the session. */
+int cwt_stream_open(cwt_server *srv, const cwt_plan *plan, int64_t C, int64_t hop,
+                    cwt_session **out);
+
+/* Append m samples per channel (host, row-major [C][m], copied before
+ * return).  Every completed hop is queued for the worker; t_arrival_ns
+ * (CLOCK_MONOTONIC, 0 = now) is the time stamp reported with its result.
+ * Returns CWT_E_AGAIN (nothing consumed) when the session already has
+ * max_pending hops queued or the push would complete more than that. */
+int cwt_stream_push(cwt_session *s, const float *samples, int64_t m, uint64_t t_arrival_ns);
+
+/* Oldest completed result: bp receives [C][n_bands] floats (host), hop_idx
+ * the hop's index since the session opened (0-based, counting every hop),
+ * t_push_ns / t_done_ns the arrival and completion times.  Any output
+ * pointer may be NULL.  Returns CWT_E_AGAIN when nothing is ready. */
+int cwt_stream_poll(cwt_session *s, float *bp, uint64_t *hop_idx, uint64_t *t_push_ns,
+                    uint64_t *t_done_ns);
+
+/* Block until every hop queued so far on the server has been processed. */
+int cwt_server_flush(cwt_server *srv);
+
+/* Close a session (its queued hops are dropped) and release its ring. */
+int cwt_stream_close(cwt_session *s);
+
+int cwt_server_get_stats(const cwt_server *srv, cwt_server_stats *stats);
+
+/* CLOCK_MONOTONIC in nanoseconds (the clock of the stream time stamps). */
+uint64_t cwt_now_ns(void);
+
 /* Release the plan.  Synchronises `stream` first, so work already enqueued
  * on it that uses the plan completes before the tables are freed; work on
  * other streams that uses the plan must be complete before this call. */

@@ -65,6 +65,21 @@ class PlanDesc(ctypes.Structure):
     ]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [
+        ("max_batch", ctypes.c_int32),
+        ("deadline_us", ctypes.c_int32),
+        ("max_pending", ctypes.c_int32),
+        ("reserved_", ctypes.c_int32),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "batches", "hops", "results", "rejected", "sessions_open", "hbm_bytes_used",
+        "hbm_budget_bytes")]
+
+
 class CwtError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s (%d): %s" % (ERROR_NAMES.get(code, "CWT_E?"), code, msg))
@@ -93,6 +108,19 @@ SIGNATURES = {
                                             ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_float), _VP]),
     "cwt_plan_destroy": (ctypes.c_int, [_VP, _VP]),
+    "cwt_server_opts_init": (ctypes.c_int, [ctypes.POINTER(ServerOpts)]),
+    "cwt_server_create": (ctypes.c_int, [ctypes.POINTER(_VP), _SZ, ctypes.POINTER(ServerOpts)]),
+    "cwt_server_destroy": (ctypes.c_int, [_VP]),
+    "cwt_stream_open": (ctypes.c_int, [_VP, _VP, _I64, _I64, ctypes.POINTER(_VP)]),
+    "cwt_stream_push": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float), _I64, ctypes.c_uint64]),
+    "cwt_stream_poll": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float),
+                                       ctypes.POINTER(ctypes.c_uint64),
+                                       ctypes.POINTER(ctypes.c_uint64),
+                                       ctypes.POINTER(ctypes.c_uint64)]),
+    "cwt_server_flush": (ctypes.c_int, [_VP]),
+    "cwt_stream_close": (ctypes.c_int, [_VP]),
+    "cwt_server_get_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ServerStats)]),
+    "cwt_now_ns": (ctypes.c_uint64, []),
     "cwt_last_error": (ctypes.c_char_p, []),
 }
 

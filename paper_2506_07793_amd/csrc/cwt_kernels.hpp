@@ -56,6 +56,42 @@ struct MainParams {
     int variant;           // register-resident kernel: 0 table twiddles, 1 power twiddles
 };
 
+// ----------------------------------------------------------- streaming --
+// One completed hop of one session.
+struct StreamJob {
+    float *ring;   // session ring [C][W]
+    int pos;       // ring position of this hop's first sample
+    int slab_off;  // offset of this hop's [C][hop] samples in the slab
+    int emit_row;  // row block in the window batch (>= 0 when output is due)
+    int pad_;
+};
+
+struct StreamParams {
+    const StreamJob *jobs;
+    int n_jobs;
+    const float *slab;  // [n_jobs][C][hop] new samples
+    float *xb;          // [n_emit][C][W] unrolled windows (oldest sample first)
+    int C, W, hop;
+};
+
+// Band power of the trailing hop of each window, by a direct partial
+// inverse DFT over the stored spectrum bins (only hop outputs are needed).
+struct StreamBPParams {
+    const float2 *Xh;      // [rows][Lh]
+    int Lh, L, W, hop, rows;
+    const float *H;
+    const BandDesc *band;
+    const float2 *tw;
+    const int *grp_freq;
+    const int *grp_off;
+    int n_bands;
+    float *out;            // [rows][n_bands]
+};
+
+hipError_t launch_stream_append(const StreamParams &p, hipStream_t s);
+hipError_t launch_stream_gather(const StreamParams &p, hipStream_t s);
+hipError_t launch_stream_bandpower(const StreamBPParams &p, int max_bins, hipStream_t s);
+
 // FP64 generators (run once per plan).
 struct GenParams {
     double sfreq;

@@ -1,0 +1,129 @@
+// HIP kernels of the streaming form: ring append, window gather and the
+// trailing-hop band power of each window.
+//
+// A session keeps the last W samples of each channel in a device ring.  Each
+// completed hop appends its samples; once W samples have arrived, the window
+// (oldest sample first) is transformed: the forward FFT of the window uses
+// the plain path's kernel, and this file's k_stream_bandpower evaluates the
+// inverse transform only at the hop's trailing samples t = W - hop .. W - 1,
+//   W_f[t] = sum over stored bins b of X~[b] H_f[b] exp(2 pi i b t / L),
+// then averages |W_f[t]|^2 over the band's frequencies and over those t.
+#include "cwt_kernels.hpp"
+#include "fft_core.hpp"
+
+namespace cwtk {
+
+__global__ void k_stream_append(StreamParams p)
+{
+    const StreamJob jb = p.jobs[blockIdx.x];
+    const int c = blockIdx.y;
+    const float *src = p.slab + jb.slab_off + (int64_t)c * p.hop;
+    float *ring = jb.ring + (int64_t)c * p.W;
+    for (int k = threadIdx.x; k < p.hop; k += blockDim.x) {
+        int q = jb.pos + k;
+        if (q >= p.W) q -= p.W;
+        ring[q] = src[k];
+    }
+}
+
+__global__ void k_stream_gather(StreamParams p)
+{
+    const StreamJob jb = p.jobs[blockIdx.x];
+    if (jb.emit_row < 0) return;
+    const int c = blockIdx.y;
+    const float *ring = jb.ring + (int64_t)c * p.W;
+    float *dst = p.xb + ((int64_t)jb.emit_row * p.C + c) * p.W;
+    // oldest sample sits just after the newly appended hop
+    int start = jb.pos + p.hop;
+    if (start >= p.W) start -= p.W;
+    for (int k = threadIdx.x; k < p.W; k += blockDim.x) {
+        int q = start + k;
+        if (q >= p.W) q -= p.W;
+        dst[k] = ring[q];
+    }
+}
+
+hipError_t launch_stream_append(const StreamParams &p, hipStream_t s)
+{
+    if (p.n_jobs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stream_append, dim3(p.n_jobs, p.C), dim3(128), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_gather(const StreamParams &p, hipStream_t s)
+{
+    if (p.n_jobs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stream_gather, dim3(p.n_jobs, p.C), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+// One workgroup per (window, channel) row; lane t handles trailing samples
+// t, t + T, ... < hop.  Band products for one frequency are staged in LDS and
+// read by every lane; twiddles exp(2 pi i b t / L) come from the table with
+// the index advanced exactly in integers.
+__global__ void __launch_bounds__(128) k_stream_bandpower(StreamBPParams p)
+{
+    extern __shared__ cf ys[];
+    __shared__ float red[128];
+    const int row = blockIdx.x;
+    const int tid = threadIdx.x, T = blockDim.x;
+    const int L = p.L, Lh = p.Lh;
+    const cf *X = reinterpret_cast<const cf *>(p.Xh) + (int64_t)row * Lh;
+    const cf *tw = reinterpret_cast<const cf *>(p.tw);
+    const int t0 = p.W - p.hop;
+    for (int bnd = 0; bnd < p.n_bands; ++bnd) {
+        const int qb = p.grp_off[bnd], qe = p.grp_off[bnd + 1];
+        float psum = 0.f;
+        for (int q = qb; q < qe; ++q) {
+            const BandDesc bd = p.band[p.grp_freq[q]];
+            const float *Hf = p.H + bd.off;
+            const int K = bd.K;
+            const int lo_u = bd.lo < 0 ? bd.lo + L : bd.lo;
+            __syncthreads();  // previous frequency finished with ys
+            for (int k = tid; k < K; k += T) {
+                int b = lo_u + k;
+                if (b >= L) b -= L;
+                const bool upper = 2 * b > L;
+                cf xv = X[upper ? L - b : b];
+                if (upper) xv.y = -xv.y;
+                ys[k] = scale(xv, Hf[k]);
+            }
+            __syncthreads();
+            for (int t = tid; t < p.hop; t += T) {
+                const int ta = t0 + t;
+                int idx = (int)(((int64_t)lo_u * ta) % L);
+                float ar = 0.f, ai = 0.f;
+                for (int k = 0; k < K; ++k) {
+                    const cf y = ys[k];
+                    const cf w = tw[idx];
+                    ar += y.x * w.x - y.y * w.y;
+                    ai += y.x * w.y + y.y * w.x;
+                    idx += ta;
+                    if (idx >= L) idx -= L;
+                }
+                psum += ar * ar + ai * ai;
+            }
+        }
+        red[tid] = psum;
+        __syncthreads();
+        for (int s = T / 2; s > 0; s >>= 1) {
+            if (tid < s) red[tid] += red[tid + s];
+            __syncthreads();
+        }
+        if (tid == 0)
+            p.out[(int64_t)row * p.n_bands + bnd] = red[0] / ((float)(qe - qb) * (float)p.hop);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_stream_bandpower(const StreamBPParams &p, int max_bins, hipStream_t s)
+{
+    if (p.rows == 0) return hipSuccess;
+    const size_t lds = (size_t)(max_bins > 0 ? max_bins : 1) * sizeof(cf);
+    (void)hipFuncSetAttribute((const void *)k_stream_bandpower,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_stream_bandpower, dim3(p.rows), dim3(128), lds, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace cwtk

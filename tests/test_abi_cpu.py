@@ -162,3 +162,28 @@ def test_spectrum_band_covers_threshold():
         need += int(np.sum(H >= 1e-12 * H.max()))
     assert d.spectrum_bins >= need
     assert d.spectrum_bins <= 2 * need  # the band is not wastefully wide
+
+
+def test_stream_validation_without_gpu():
+    """Server/stream entry points reject bad arguments before any device call."""
+    lib = _lib.load()
+    INV = _lib.CWT_E_INVALID
+    h = ctypes.c_void_p()
+    assert lib.cwt_server_create(None, 1 << 20, None) == INV
+    o = _lib.ServerOpts()
+    lib.cwt_server_opts_init(ctypes.byref(o))
+    assert (o.max_batch, o.deadline_us, o.max_pending) == (256, 1000, 64)
+    o.max_batch = 0
+    assert lib.cwt_server_create(ctypes.byref(h), 1 << 20, ctypes.byref(o)) == INV
+    lib.cwt_server_opts_init(ctypes.byref(o))
+    assert lib.cwt_server_create(ctypes.byref(h), 0, ctypes.byref(o)) == INV
+    assert not h.value
+    assert lib.cwt_stream_open(None, None, 1, 1, ctypes.byref(h)) == INV
+    assert lib.cwt_stream_push(None, None, 10, 0) == INV
+    assert lib.cwt_stream_poll(None, None, None, None, None) == INV
+    assert lib.cwt_server_flush(None) == INV
+    assert lib.cwt_stream_close(None) == _lib.CWT_OK
+    assert lib.cwt_server_destroy(None) == _lib.CWT_OK
+    t1 = lib.cwt_now_ns()
+    t2 = lib.cwt_now_ns()
+    assert t2 >= t1 > 0

@@ -1,0 +1,167 @@
+"""Streaming server on the GPU: trailing-hop band power vs the FP64 oracle,
+batching across sessions, HBM-budget admission and backpressure."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2506_07793_amd as cwt
+from paper_2506_07793_amd import _lib
+from paper_2506_07793_amd.stream import Server, now_ns
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    yield
+
+
+def _plan(W, sfreq, F, fmax):
+    freqs = synth.log_freqs(1.0, fmax, F)
+    cyc = synth.eeg_cycles(freqs)
+    return cwt.Plan(W, sfreq, freqs, n_cycles=cyc, out="bandpower"), freqs, cyc
+
+
+def _check(results, x, W, hop, sfreq, freqs, cyc, label, max_checks=None):
+    """results: list of (bp, hop_idx); x: the full pushed signal [C, T]."""
+    assert results, "no results"
+    worst = 0.0
+    checked = 0
+    for bp, h in results:
+        end = (h + 1) * hop
+        assert end >= W
+        win = x[:, end - W:end].astype(np.float64)
+        ref = oracle.stream_band_power(win, sfreq, freqs, cyc, hop)
+        scale = np.maximum(ref.max(axis=0, keepdims=True), 1e-30)
+        e = float(np.max(np.abs(bp - ref) / scale))
+        worst = max(worst, e)
+        checked += 1
+        if max_checks and checked >= max_checks:
+            break
+    print("%s: %d windows, worst per-band relative error %.3e" % (label, checked, worst))
+    assert worst <= TOL
+
+
+def test_single_session_matches_oracle():
+    W, hop, sfreq, C = 500, 25, 250.0, 3
+    plan, freqs, cyc = _plan(W, sfreq, 12, 100.0)
+    srv = Server(1 << 30, max_batch=8, deadline_us=200)
+    s = srv.open(plan, C, hop)
+    x = synth.eeg(C, 1500, sfreq, seed=7)
+    rng = np.random.default_rng(0)
+    pos = 0
+    while pos < x.shape[1]:  # ragged pushes: partial hops and several hops at once
+        m = int(rng.integers(1, 60))
+        m = min(m, x.shape[1] - pos)
+        assert s.push(x[:, pos:pos + m])
+        pos += m
+        if rng.random() < 0.3:
+            srv.flush()
+    srv.flush()
+    res = []
+    while True:
+        r = s.poll()
+        if r is None:
+            break
+        res.append((r[0], r[1]))
+    # one result per hop once the window is full: hops 19 .. 59
+    assert [h for _, h in res] == list(range(W // hop - 1, x.shape[1] // hop))
+    _check(res, x, W, hop, sfreq, freqs, cyc, "single session")
+    st = srv.stats()
+    assert st["results"] == len(res) and st["hops"] == x.shape[1] // hop
+    srv.close()
+    plan.close()
+
+
+def test_many_sessions_batched():
+    W, hop, sfreq, C = 1000, 50, 500.0, 4
+    plan, freqs, cyc = _plan(W, sfreq, 16, 120.0)
+    srv = Server(1 << 31, max_batch=16, deadline_us=2000)
+    sess = [srv.open(plan, C, hop) for _ in range(10)]
+    xs = [synth.eeg(C, 2000, sfreq, seed=100 + i) for i in range(10)]
+    for k in range(0, 2000, hop):  # interleaved pushes of one hop each
+        for s, x in zip(sess, xs):
+            assert s.push(x[:, k:k + hop])
+    srv.flush()
+    for i, (s, x) in enumerate(zip(sess, xs)):
+        res = []
+        while True:
+            r = s.poll()
+            if r is None:
+                break
+            res.append((r[0], r[1]))
+        assert len(res) == 2000 // hop - W // hop + 1
+        _check(res, x, W, hop, sfreq, freqs, cyc, "session %d" % i, max_checks=6)
+    st = srv.stats()
+    assert st["batches"] < st["hops"]  # hops of different sessions shared launches
+    srv.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("W,hop,sfreq,C,F", [(2000, 50, 1000.0, 64, 40), (4096, 102, 2048.0, 256, 40)])
+def test_config4_shapes(W, hop, sfreq, C, F):
+    """Serving shapes: 64 ch x 2 s at 1000 Hz (hop 50) and 256 ch x 2 s at 2048 Hz (hop 102)."""
+    plan, freqs, cyc = _plan(W, sfreq, F, 100.0)
+    srv = Server(8 << 30, max_batch=4, deadline_us=500)
+    s = srv.open(plan, C, hop)
+    x = synth.eeg(C, W + 2 * hop, sfreq, seed=9)
+    assert s.push(x)
+    srv.flush()
+    res = []
+    while True:
+        r = s.poll()
+        if r is None:
+            break
+        res.append((r[0], r[1]))
+    n_hops = (W + 2 * hop) // hop
+    assert [h for _, h in res] == [h for h in range(n_hops) if (h + 1) * hop >= W]
+    _check(res, x, W, hop, sfreq, freqs, cyc, "W=%d C=%d" % (W, C), max_checks=1)
+    srv.close()
+    plan.close()
+
+
+def test_budget_backpressure_and_close():
+    W, hop, sfreq, C = 500, 25, 250.0, 2
+    plan, freqs, cyc = _plan(W, sfreq, 8, 100.0)
+    srv = Server(4 << 20, max_batch=4, max_pending=3)
+    opened = []
+    with pytest.raises(cwt.CwtError) as ei:
+        for _ in range(1000):
+            opened.append(srv.open(plan, C, hop))
+    assert ei.value.code == _lib.CWT_E_BUDGET
+    assert 1 <= len(opened) < 1000
+    st = srv.stats()
+    assert st["hbm_bytes_used"] <= st["hbm_budget_bytes"]
+    s = opened[0]
+    # a push that would complete more than max_pending hops is refused whole
+    assert not s.push(np.zeros((C, 4 * hop), np.float32))
+    assert srv.stats()["rejected"] == 1
+    assert s.push(np.zeros((C, 2 * hop), np.float32))
+    # closing a session releases its ring: one more session fits again
+    opened[-1].close()
+    opened.append(srv.open(plan, C, hop))
+    t0 = now_ns()
+    srv.flush()
+    assert now_ns() >= t0
+    srv.close()  # closes the remaining sessions
+    plan.close()
+
+
+def test_open_rejects_bad_arguments():
+    plan_c = cwt.Plan(500, 250.0, [10.0, 20.0], n_cycles=5.0)  # complex output
+    plan_b, _, _ = _plan(500, 250.0, 8, 100.0)
+    srv = Server(1 << 30)
+    for args, code in (((plan_c, 2, 25), _lib.CWT_E_INVALID), ((plan_b, 0, 25), _lib.CWT_E_INVALID),
+                       ((plan_b, 2, 0), _lib.CWT_E_INVALID), ((plan_b, 2, 501), _lib.CWT_E_INVALID)):
+        with pytest.raises(cwt.CwtError) as ei:
+            srv.open(*args)
+        assert ei.value.code == code
+    srv.close()
+    plan_c.close()
+    plan_b.close()
