@@ -38,10 +38,118 @@ def parse():
                     help="channels of the oracle's timed sample (all 100 frequencies each)")
     ap.add_argument("--graph", type=int, default=0,
                     help="1: replay the step as a captured HIP graph; 0: direct launches (default)")
+    ap.add_argument("--stream-seconds", type=float, default=6.0,
+                    help="real-time length of each streaming run (0 skips the streaming runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (scales the HBM "
                          "byte counters of a profiler run)")
     return ap.parse_args()
+
+
+def bench_stream(n_sessions, C, sfreq, win_s, hop_s, seconds, seed, max_batch, deadline_us):
+    """Real-time serving run: Poisson-arriving sessions push one hop each hop_s.
+
+    n_sessions sessions are open at t = 0; new ones arrive at rate
+    n_sessions / 20 s and live an exponential 20 s on average, so about
+    n_sessions stay open.  Each session arrives with its window already
+    filled (its past samples pushed at open), then pushes one hop every hop_s
+    at a random phase.  Latency = result completion - push of the hop's last
+    sample, both on CLOCK_MONOTONIC.
+    """
+    import numpy as np
+
+    import paper_2506_07793_amd as cwt
+    import synth
+    from paper_2506_07793_amd.stream import Server, now_ns
+
+    W = int(round(win_s * sfreq))
+    hop = int(round(hop_s * sfreq))
+    freqs = synth.log_freqs(1.0, 100.0, 40)
+    plan = cwt.Plan(W, sfreq, freqs, n_cycles=synth.eeg_cycles(freqs), out="bandpower")
+    pool = synth.eeg(C, int(30 * sfreq), sfreq, seed)  # shared signal, each session at its own offset
+    T = pool.shape[1]
+    sched = synth.session_schedule(n_sessions, seconds, hop_s=hop_s, seed=seed)
+    srv = Server(64 << 30, max_batch=max_batch, deadline_us=deadline_us, max_pending=256)
+    rng = np.random.default_rng(seed)
+    events = []  # (time, kind, index)
+    for i, (t_open, t_close, phase) in enumerate(sched):
+        events.append((t_open, 0, i))
+        events.append((min(t_close, seconds), 2, i))
+    events.sort()
+    sess, offs, nxt, outstanding = {}, {}, {}, {}
+    lat = []
+    t0 = time.perf_counter()
+    hop_times = []  # heap of (t, i)
+    import heapq
+
+    def drain(all_=False):
+        for i, s in list(sess.items()):
+            if outstanding.get(i, 0) == 0:
+                continue
+            while True:
+                r = s.poll()
+                if r is None:
+                    break
+                lat.append((r[3] - r[2]) * 1e-6)
+                outstanding[i] -= 1
+
+    ev = 0
+    last_drain = 0.0
+    pushed = 0
+    while True:
+        now = time.perf_counter() - t0
+        if now >= seconds:
+            break
+        while ev < len(events) and events[ev][0] <= now:
+            _, kind, i = events[ev]
+            ev += 1
+            if kind == 0:
+                s = srv.open(plan, C, hop)
+                o = int(rng.integers(0, T - W))
+                s.push(pool[:, o:o + W - hop])  # history: the window minus one hop
+                sess[i], offs[i] = s, o + W - hop
+                outstanding[i] = 0
+                heapq.heappush(hop_times, (now + sched[i][2], i))
+            elif i in sess:
+                s = sess.pop(i)
+                s.close()
+        while hop_times and hop_times[0][0] <= now:
+            t_h, i = heapq.heappop(hop_times)
+            if i not in sess:
+                continue
+            o = offs[i]
+            if o + hop > T:
+                o = 0
+            if sess[i].push(pool[:, o:o + hop]):
+                outstanding[i] += 1
+                pushed += 1
+            offs[i] = o + hop
+            heapq.heappush(hop_times, (t_h + hop_s, i))
+        if now - last_drain > 0.005:
+            drain()
+            last_drain = now
+        nt = min(hop_times[0][0] if hop_times else now + 0.001,
+                 events[ev][0] if ev < len(events) else now + 0.001)
+        if nt > now:
+            time.sleep(min(nt - now, 0.001))
+    srv.flush()
+    drain()
+    st = srv.stats()
+    elapsed = time.perf_counter() - t0
+    for s in list(sess.values()):
+        s.close()
+    srv.close()
+    plan.close()
+    lat = np.array(lat)
+    return {
+        "workload": "%d sessions x %d ch @%g Hz, %g s window, %g ms hop, 40 log freqs 1-100 Hz, "
+                    "band power" % (n_sessions, C, sfreq, win_s, hop_s * 1e3),
+        "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
+        "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
+        "p999_ms": float(np.percentile(lat, 99.9)) if lat.size else None,
+        "results": int(lat.size), "hops_pushed": pushed, "hops_per_s": pushed / elapsed,
+        "batches": st["batches"], "mean_batch": st["hops"] / max(1, st["batches"]),
+        "seconds": seconds, "max_batch": max_batch, "deadline_us": deadline_us}
 
 
 def main():
@@ -144,7 +252,8 @@ def main():
     step_bytes = main_bytes + C * N * 4 + C * Lh * 8
 
     result = {
-        "metric": "CWT output samples x freqs per second",
+        "metric": "CWT output samples x freqs per second (+ %HBM roofline; p99 stream window "
+                  "latency)",
         "value": value,
         "unit": "samples*freqs/s",
         "n_gpus": 1,
@@ -170,6 +279,13 @@ def main():
                           "GBps": out.numel() * out.element_size() / (ms_fill * 1e-3) / 1e9,
                           "ms": ms_fill},
     }
+
+    if args.stream_seconds > 0:
+        result["stream"] = [
+            bench_stream(512, 64, 1000.0, 2.0, 0.05, args.stream_seconds, 5, 512, 1000),
+            bench_stream(64, 256, 2048.0, 2.0, 102 / 2048.0, args.stream_seconds, 6, 64, 1000),
+        ]
+        result["p99_stream_ms"] = result["stream"][0]["p99_ms"]
 
     if not args.no_cpu_baseline:
         import oracle

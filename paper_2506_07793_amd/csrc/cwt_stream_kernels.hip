@@ -122,7 +122,9 @@ hipError_t launch_stream_bandpower(const StreamBPParams &p, int max_bins, hipStr
     const size_t lds = (size_t)(max_bins > 0 ? max_bins : 1) * sizeof(cf);
     (void)hipFuncSetAttribute((const void *)k_stream_bandpower,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_stream_bandpower, dim3(p.rows), dim3(128), lds, s, p);
+    // one wave covers hops up to 64 samples; longer hops use two
+    const int threads = p.hop <= 64 ? 64 : 128;
+    hipLaunchKernelGGL(k_stream_bandpower, dim3(p.rows), dim3(threads), lds, s, p);
     return hipGetLastError();
 }
 

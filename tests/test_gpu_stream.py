@@ -128,8 +128,8 @@ def test_config4_shapes(W, hop, sfreq, C, F):
 
 def test_budget_backpressure_and_close():
     W, hop, sfreq, C = 500, 25, 250.0, 2
-    plan, freqs, cyc = _plan(W, sfreq, 8, 100.0)
-    srv = Server(4 << 20, max_batch=4, max_pending=3)
+    plan, freqs, cyc = _plan(W, sfreq, 12, 100.0)
+    srv = Server(1 << 20, max_batch=4, max_pending=3)
     opened = []
     with pytest.raises(cwt.CwtError) as ei:
         for _ in range(1000):
@@ -155,7 +155,7 @@ def test_budget_backpressure_and_close():
 
 def test_open_rejects_bad_arguments():
     plan_c = cwt.Plan(500, 250.0, [10.0, 20.0], n_cycles=5.0)  # complex output
-    plan_b, _, _ = _plan(500, 250.0, 8, 100.0)
+    plan_b, _, _ = _plan(500, 250.0, 12, 100.0)
     srv = Server(1 << 30)
     for args, code in (((plan_c, 2, 25), _lib.CWT_E_INVALID), ((plan_b, 0, 25), _lib.CWT_E_INVALID),
                        ((plan_b, 2, 0), _lib.CWT_E_INVALID), ((plan_b, 2, 501), _lib.CWT_E_INVALID)):
