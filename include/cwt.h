@@ -181,6 +181,38 @@ int cwt_transform_spectra(const cwt_plan *plan, int64_t C, void *out, void *ws,
 int cwt_plan_copy_tables(const cwt_plan *plan, float *H_host, int32_t *band_host,
                          float *tw_host, void *stream);
 
+/* ---- batches ---------------------------------------------------------- */
+/*
+ * Many recordings at once, each with its own plan (length, sampling rate,
+ * frequency grid, output mode), channel count and device buffers, as in the
+ * paper's use on EEG recordings of different lengths (section "Wavelength
+ * and flexibility").  x and out have the same layouts as for cwt_execute.
+ */
+typedef struct cwt_batch_item {
+    const cwt_plan *plan;  /* FP32 plan                                        */
+    const float *x;        /* device [C][plan n]                               */
+    int64_t C;             /* channels (0 = skip)                              */
+    void *out;             /* device output, cwt_execute layout                */
+} cwt_batch_item;
+
+/* Device workspace bytes cwt_execute_batch needs for these items (tables,
+ * task lists and per-item spectra).  Returns 0 on invalid items. */
+size_t cwt_batch_workspace_size(const cwt_batch_item *items, int32_t n);
+
+/*
+ * Transform every item with one HIP graph launch of persistent kernels:
+ * tasks (channel pairs for the forward transforms, (channel, output row) for
+ * the transforms) are grouped by workgroup size and claimed by resident
+ * workgroups through atomic counters, longest first.  The graph is captured
+ * the first time a (workspace, task layout) pair is seen and replayed
+ * afterwards; the per-item tables are uploaded into ws on `stream` before
+ * each launch.  Asynchronous; the items' buffers must not overlap each other
+ * or ws.  The environment variable CWT_BATCH_GRAPH=0 launches the kernels
+ * directly instead of through the graph.
+ */
+int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *ws, size_t ws_bytes,
+                      void *stream);
+
 /* ---- streaming ------------------------------------------------------- */
 /*
  * Real-time form (the paper's real-time EEG use, sections "Introduction" and

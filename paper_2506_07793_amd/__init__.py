@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import CwtError  # noqa: F401
 
-__all__ = ["Plan", "CwtError", "cwt", "describe", "DEFAULT_BANDS"]
+__all__ = ["Plan", "Batch", "CwtError", "cwt", "describe", "DEFAULT_BANDS"]
 
 DEFAULT_BANDS = ((1.0, 4.0), (4.0, 8.0), (8.0, 13.0), (13.0, 30.0), (30.0, 100.0))
 
@@ -196,6 +196,39 @@ class Plan:
     @property
     def handle(self):
         return self._ptr
+
+
+class Batch:
+    """Many (plan, x, out) items in one graph launch of persistent kernels."""
+
+    def __init__(self, items):
+        """items: list of (plan, x [C, n] cuda float32, out tensor)."""
+        self.items = list(items)
+        self._arr = (_lib.BatchItem * max(1, len(self.items)))()
+        for i, (plan, x, out) in enumerate(self.items):
+            if x.dtype.is_floating_point is False or not x.is_contiguous():
+                raise TypeError("x must be a contiguous float32 tensor")
+            if x.shape[-1] != plan.n:
+                raise ValueError("item %d: x has %d samples, plan expects %d" % (
+                    i, x.shape[-1], plan.n))
+            if tuple(out.shape) != plan.output_shape(x.shape[0]):
+                raise ValueError("item %d: out must have shape %s" % (
+                    i, plan.output_shape(x.shape[0])))
+            self._arr[i] = _lib.BatchItem(plan.handle.value, x.data_ptr(), int(x.shape[0]),
+                                          out.data_ptr())
+        self._lib = _lib.load()
+
+    def workspace_size(self):
+        return int(self._lib.cwt_batch_workspace_size(self._arr, len(self.items)))
+
+    def alloc_workspace(self, device="cuda"):
+        import torch
+        return torch.empty(max(256, self.workspace_size()), dtype=torch.uint8, device=device)
+
+    def execute(self, ws, stream=None):
+        _lib.check(self._lib.cwt_execute_batch(self._arr, len(self.items), _dptr(ws),
+                                               ws.numel() * ws.element_size(),
+                                               _stream_handle(stream)))
 
 
 def cwt(x, sfreq, freqs, n_cycles, **kw):

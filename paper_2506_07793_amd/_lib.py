@@ -80,6 +80,15 @@ class ServerStats(ctypes.Structure):
         "hbm_budget_bytes")]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [
+        ("plan", ctypes.c_void_p),
+        ("x", ctypes.c_void_p),
+        ("C", ctypes.c_int64),
+        ("out", ctypes.c_void_p),
+    ]
+
+
 class CwtError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s (%d): %s" % (ERROR_NAMES.get(code, "CWT_E?"), code, msg))
@@ -108,6 +117,8 @@ SIGNATURES = {
                                             ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_float), _VP]),
     "cwt_plan_destroy": (ctypes.c_int, [_VP, _VP]),
+    "cwt_batch_workspace_size": (_SZ, [ctypes.POINTER(BatchItem), _I32]),
+    "cwt_execute_batch": (ctypes.c_int, [ctypes.POINTER(BatchItem), _I32, _VP, _SZ, _VP]),
     "cwt_server_opts_init": (ctypes.c_int, [ctypes.POINTER(ServerOpts)]),
     "cwt_server_create": (ctypes.c_int, [ctypes.POINTER(_VP), _SZ, ctypes.POINTER(ServerOpts)]),
     "cwt_server_destroy": (ctypes.c_int, [_VP]),

@@ -1,0 +1,342 @@
+// Batched form of libcwt: recordings of uneven length, channel count and
+// frequency grid in one graph launch of persistent kernels.
+//
+// The host builds, in the caller's workspace, a parameter table per item and
+// two task lists (channel pairs for the forward transforms, (channel, row)
+// for the transforms), sorted by estimated cost so that the long tasks start
+// first.  Tasks are grouped into classes by workgroup size; each class runs
+// one persistent forward kernel and one persistent transform kernel whose
+// workgroups claim tasks through an atomic counter.  The launches are
+// captured once into a HIP graph per (workspace, layout) and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "../../include/cwt.h"
+#include "cwt_internal.hpp"
+#include "cwt_kernels.hpp"
+
+using namespace cwtk;
+using namespace cwtrt;
+
+namespace {
+
+size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Workgroup-size classes: a task may run with more threads than its plan
+// needs (each thread then holds fewer butterflies), never fewer.
+int class_threads(int t)
+{
+    for (int c : {64, 128, 256, 512, 1024})
+        if (t <= c) return c;
+    return 1024;
+}
+
+struct ClassInfo {
+    int threads = 0, maxv = 16;
+    int max_L = 1;
+    std::vector<BatchTask> fwd, main;
+};
+
+struct Layout {
+    size_t counters = 0, fwd_items = 0, main_items = 0, fwd_tasks = 0, main_tasks = 0, xh = 0,
+           total = 0;
+    std::vector<size_t> xh_off;  // per item, bytes from ws
+};
+
+Layout make_layout(const cwt_batch_item *items, int n, size_t n_fwd, size_t n_main)
+{
+    Layout Lo;
+    size_t off = 0;
+    Lo.counters = off;
+    off += al(64 * sizeof(int));
+    Lo.fwd_items = off;
+    off += al((size_t)n * sizeof(FwdParams));
+    Lo.main_items = off;
+    off += al((size_t)n * sizeof(MainParams));
+    Lo.fwd_tasks = off;
+    off += al(n_fwd * sizeof(BatchTask));
+    Lo.main_tasks = off;
+    off += al(n_main * sizeof(BatchTask));
+    Lo.xh = off;
+    Lo.xh_off.resize(n);
+    for (int i = 0; i < n; ++i) {
+        Lo.xh_off[i] = off;
+        off += workspace_bytes(*items[i].plan, items[i].C);
+    }
+    Lo.total = off;
+    return Lo;
+}
+
+int validate(const cwt_batch_item *items, int n)
+{
+    if (n < 0) return fail(CWT_E_INVALID, "n must be >= 0");
+    if (n > 0 && !items) return fail(CWT_E_INVALID, "items is NULL");
+    for (int i = 0; i < n; ++i) {
+        const cwt_batch_item &it = items[i];
+        if (!it.plan) return fail(CWT_E_INVALID, "items[%d].plan is NULL", i);
+        if (it.C < 0 || it.C > (int64_t)1 << 24) return fail(CWT_E_INVALID, "items[%d].C out of range", i);
+        if (it.C > 0 && (!it.x || !it.out))
+            return fail(CWT_E_INVALID, "items[%d] has a NULL device pointer", i);
+        if (it.plan->opts.precision != CWT_PREC_FP32)
+            return fail(CWT_E_UNSUPPORTED, "items[%d]: batches run the FP32 path", i);
+        const int64_t rows =
+            (it.plan->opts.out == CWT_OUT_BANDPOWER_F32) ? it.plan->n_bands : it.plan->F;
+        if (it.C * rows > (int64_t)INT32_MAX)
+            return fail(CWT_E_UNSUPPORTED, "items[%d]: C x rows exceeds the task range", i);
+    }
+    return CWT_OK;
+}
+
+// Graph cache: one instantiated graph per (workspace, layout, classes).
+struct GraphKey {
+    void *ws;
+    int device;
+    std::vector<int64_t> shape;
+    bool operator<(const GraphKey &o) const
+    {
+        return std::tie(ws, device, shape) < std::tie(o.ws, o.device, o.shape);
+    }
+};
+
+struct GraphCache {
+    std::mutex mu;
+    std::map<GraphKey, hipGraphExec_t> execs;
+    std::map<int, hipStream_t> cap_streams;
+};
+
+GraphCache &cache()
+{
+    static GraphCache *c = new GraphCache();  // lives until process exit
+    return *c;
+}
+
+// Pinned host staging of the tables, one per device, reused after the
+// previous upload from it has completed.
+struct Staging {
+    std::mutex mu;
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+
+Staging &staging(int dev)
+{
+    static std::mutex m;
+    static std::map<int, Staging *> s;
+    std::lock_guard<std::mutex> lk(m);
+    Staging *&p = s[dev];
+    if (!p) p = new Staging();
+    return *p;
+}
+
+int enqueue_kernels(const std::vector<ClassInfo> &classes, char *ws, const Layout &Lo,
+                    hipStream_t s)
+{
+    hipError_t e = launch_zero_counters(reinterpret_cast<int *>(ws + Lo.counters),
+                                        2 * (int)classes.size(), s);
+    if (e != hipSuccess) return hip_fail(e, "counter reset");
+    size_t f_off = 0, m_off = 0;
+    for (size_t k = 0; k < classes.size(); ++k) {
+        const ClassInfo &c = classes[k];
+        int *ctr = reinterpret_cast<int *>(ws + Lo.counters) + 2 * k;
+        const size_t lds = (size_t)c.max_L * sizeof(float2);
+        e = launch_batch_forward(reinterpret_cast<const FwdParams *>(ws + Lo.fwd_items),
+                                 reinterpret_cast<const BatchTask *>(ws + Lo.fwd_tasks) + f_off,
+                                 (int)c.fwd.size(), ctr, c.threads, c.maxv, lds, s);
+        if (e != hipSuccess) return hip_fail(e, "batch forward launch");
+        e = launch_batch_main(reinterpret_cast<const MainParams *>(ws + Lo.main_items),
+                              reinterpret_cast<const BatchTask *>(ws + Lo.main_tasks) + m_off,
+                              (int)c.main.size(), ctr + 1, c.threads, c.maxv, lds, s);
+        if (e != hipSuccess) return hip_fail(e, "batch transform launch");
+        f_off += c.fwd.size();
+        m_off += c.main.size();
+    }
+    return CWT_OK;
+}
+
+}  // namespace
+
+extern "C" size_t cwt_batch_workspace_size(const cwt_batch_item *items, int32_t n)
+{
+    if (validate(items, n) != CWT_OK) return 0;
+    size_t n_fwd = 0, n_main = 0;
+    for (int i = 0; i < n; ++i) {
+        const cwt_plan &P = *items[i].plan;
+        const int64_t rows = (P.opts.out == CWT_OUT_BANDPOWER_F32) ? P.n_bands : P.F;
+        n_fwd += (size_t)((items[i].C + 1) / 2);
+        n_main += (size_t)(items[i].C * rows);
+    }
+    return make_layout(items, n, n_fwd, n_main).total;
+}
+
+extern "C" int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *ws,
+                                 size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = validate(items, n);
+    if (rc != CWT_OK) return rc;
+    if (n == 0) return CWT_OK;
+    if (!ws) return fail(CWT_E_INVALID, "ws is NULL");
+    if (((uintptr_t)ws & 255) != 0) return fail(CWT_E_INVALID, "ws must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+
+    // Tasks, grouped by workgroup-size class.
+    std::map<std::pair<int, int>, ClassInfo> by_class;
+    for (int i = 0; i < n; ++i) {
+        const cwt_plan &P = *items[i].plan;
+        if (items[i].C == 0) continue;
+        const int thr = class_threads(P.rp.threads);
+        ClassInfo &c = by_class[{thr, P.rp.maxv}];
+        c.threads = thr;
+        c.maxv = P.rp.maxv;
+        c.max_L = std::max(c.max_L, P.L);
+        const int rows = (P.opts.out == CWT_OUT_BANDPOWER_F32) ? P.n_bands : P.F;
+        const double lg = std::log2((double)std::max(2, P.L));
+        const int fcost = (int)std::min(2e9, P.L * lg);
+        for (int pr = 0; pr < (int)((items[i].C + 1) / 2); ++pr) c.fwd.push_back({i, pr, 0, fcost});
+        for (int ch = 0; ch < (int)items[i].C; ++ch)
+            for (int r = 0; r < rows; ++r) {
+                int per = 1;
+                if (P.opts.out == CWT_OUT_BANDPOWER_F32) per = P.grp_off[r + 1] - P.grp_off[r];
+                c.main.push_back({i, ch, r, (int)std::min(2e9, per * P.L * lg)});
+            }
+    }
+    std::vector<ClassInfo> classes;
+    size_t n_fwd = 0, n_main = 0;
+    for (auto &kv : by_class) {
+        ClassInfo c = std::move(kv.second);
+        auto by_cost = [](const BatchTask &a, const BatchTask &b) { return a.cost > b.cost; };
+        std::stable_sort(c.fwd.begin(), c.fwd.end(), by_cost);
+        std::stable_sort(c.main.begin(), c.main.end(), by_cost);
+        n_fwd += c.fwd.size();
+        n_main += c.main.size();
+        classes.push_back(std::move(c));
+    }
+    if (classes.size() > 32) return fail(CWT_E_UNSUPPORTED, "too many task classes");
+    const Layout Lo = make_layout(items, n, n_fwd, n_main);
+    if (ws_bytes < Lo.total)
+        return fail(CWT_E_INVALID, "workspace too small: %zu < %zu bytes", ws_bytes, Lo.total);
+
+    // Host tables.
+    const size_t table_bytes = Lo.xh;  // everything before the spectra
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    Staging &st = staging(dev);
+    std::lock_guard<std::mutex> slk(st.mu);
+    hipError_t e;
+    if (st.done) {
+        e = hipEventSynchronize(st.done);  // previous upload from the staging buffer
+        if (e != hipSuccess) return hip_fail(e, "staging event");
+    } else {
+        e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "staging event");
+    }
+    if (st.cap < table_bytes) {
+        if (st.host) (void)hipHostFree(st.host);
+        st.host = nullptr;
+        st.cap = 0;
+        if (hipHostMalloc(&st.host, table_bytes, hipHostMallocDefault) != hipSuccess)
+            return fail(CWT_E_NOMEM, "pinned staging of %zu bytes failed", table_bytes);
+        st.cap = table_bytes;
+    }
+    char *h = static_cast<char *>(st.host);
+    std::memset(h, 0, Lo.fwd_items);
+    char *dws = static_cast<char *>(ws);
+    FwdParams *fi = reinterpret_cast<FwdParams *>(h + Lo.fwd_items);
+    MainParams *mi = reinterpret_cast<MainParams *>(h + Lo.main_items);
+    for (int i = 0; i < n; ++i) {
+        const cwt_plan &P = *items[i].plan;
+        float2 *Xh = reinterpret_cast<float2 *>(dws + Lo.xh_off[i]);
+        FwdParams f{};
+        f.x = items[i].x;
+        f.C = (int)items[i].C;
+        f.N = (int)P.n;
+        f.x_stride = P.n;
+        f.Xh = Xh;
+        f.Lh = P.L / 2 + 1;
+        f.tw = P.d_tw;
+        f.rp = P.rp;
+        fi[i] = f;
+        MainParams m{};
+        m.Xh = Xh;
+        m.Lh = P.L / 2 + 1;
+        m.H = P.d_H;
+        m.band = P.d_band;
+        m.tw = P.d_tw;
+        m.out = items[i].out;
+        m.out_mode = P.opts.out;
+        m.N = (int)P.n;
+        m.F = P.F;
+        m.C = (int)items[i].C;
+        m.n_rows = (P.opts.out == CWT_OUT_BANDPOWER_F32) ? P.n_bands : P.F;
+        m.grp_freq = P.d_grp_freq;
+        m.grp_off = P.d_grp_off;
+        m.rp = P.rp;
+        m.variant = 0;
+        mi[i] = m;
+    }
+    BatchTask *ft = reinterpret_cast<BatchTask *>(h + Lo.fwd_tasks);
+    BatchTask *mt = reinterpret_cast<BatchTask *>(h + Lo.main_tasks);
+    std::vector<int64_t> shape;
+    for (const ClassInfo &c : classes) {
+        std::copy(c.fwd.begin(), c.fwd.end(), ft);
+        ft += c.fwd.size();
+        std::copy(c.main.begin(), c.main.end(), mt);
+        mt += c.main.size();
+        shape.insert(shape.end(), {c.threads, c.maxv, c.max_L, (int64_t)c.fwd.size(),
+                                   (int64_t)c.main.size()});
+    }
+    shape.insert(shape.end(), {(int64_t)Lo.total, n});
+    e = hipMemcpyAsync(dws + Lo.fwd_items, h + Lo.fwd_items, table_bytes - Lo.fwd_items,
+                       hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "batch table upload");
+    e = hipEventRecord(st.done, s);
+    if (e != hipSuccess) return hip_fail(e, "staging event record");
+
+    // Launch: replay the cached graph, or capture one.
+    const char *g = std::getenv("CWT_BATCH_GRAPH");
+    const bool use_graph = !(g && g[0] == '0');
+    if (!use_graph) return enqueue_kernels(classes, dws, Lo, s);
+    GraphCache &gc = cache();
+    std::lock_guard<std::mutex> glk(gc.mu);
+    GraphKey key{ws, dev, shape};
+    auto it = gc.execs.find(key);
+    if (it == gc.execs.end()) {
+        hipStream_t &cs = gc.cap_streams[dev];
+        if (!cs) {
+            e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e, "capture stream");
+        }
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        rc = enqueue_kernels(classes, dws, Lo, cs);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(cs, &graph);
+        if (rc != CWT_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        if (gc.execs.size() >= 32) {  // bounded cache
+            (void)hipGraphExecDestroy(gc.execs.begin()->second);
+            gc.execs.erase(gc.execs.begin());
+        }
+        it = gc.execs.emplace(key, exec).first;
+    }
+    e = hipGraphLaunch(it->second, s);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return CWT_OK;
+}

@@ -59,12 +59,13 @@ hipError_t launch_generate(const GenParams &p, int max_bins, hipStream_t s)
 
 // --------------------------------------------------------- forward FFT --
 
+// Forward transform of channel pair `pair` (channels 2 pair, 2 pair + 1).
 template <int MAXV>
-__global__ void __launch_bounds__(1024) k_forward(FwdParams p)
+__device__ __forceinline__ void forward_task(const FwdParams &p, int pair)
 {
     extern __shared__ cf lds[];
     const int L = p.rp.L, T = blockDim.x, tid = threadIdx.x;
-    const int c0 = 2 * blockIdx.x;
+    const int c0 = 2 * pair;
     const bool has1 = (c0 + 1) < p.C;
     const float *x0 = p.x + (int64_t)c0 * p.x_stride;
     const float *x1 = p.x + (int64_t)(c0 + 1) * p.x_stride;
@@ -106,6 +107,12 @@ __global__ void __launch_bounds__(1024) k_forward(FwdParams p)
     }
 }
 
+template <int MAXV>
+__global__ void __launch_bounds__(1024) k_forward(FwdParams p)
+{
+    forward_task<MAXV>(p, blockIdx.x);
+}
+
 static void set_lds_limit(const void *fn, size_t bytes)
 {
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -127,17 +134,16 @@ hipError_t launch_forward(const FwdParams &p, hipStream_t s)
 
 // --------------------------------------------------------- main kernel --
 
+// Output row `row` of channel c: one frequency (complex / power) or one
+// band (band power, accumulated over the band's frequencies).
 template <int MAXV, int MODE>
-__global__ void __launch_bounds__(1024) k_main(MainParams p)
+__device__ __forceinline__ void main_task(const MainParams &p, int c, int row)
 {
     extern __shared__ cf lds[];
     const int L = p.rp.L, T = blockDim.x, tid = threadIdx.x;
     const int N = p.N, Lh = p.Lh;
     const int n_pass = p.rp.n_pass;
     const cf *tw = reinterpret_cast<const cf *>(p.tw);
-
-    const int c = blockIdx.x / p.n_rows;
-    const int row = blockIdx.x - c * p.n_rows;
     int qb, qe;
     if (MODE == kOutBand) {
         qb = p.grp_off[row];
@@ -216,6 +222,120 @@ __global__ void __launch_bounds__(1024) k_main(MainParams p)
             Ns *= R;
         }
     }
+}
+
+template <int MAXV, int MODE>
+__global__ void __launch_bounds__(1024) k_main(MainParams p)
+{
+    const int c = blockIdx.x / p.n_rows;
+    const int row = blockIdx.x - c * p.n_rows;
+    main_task<MAXV, MODE>(p, c, row);
+}
+
+// ----------------------------------------------------- batched, persistent --
+// Workgroups claim tasks from a counter until the list is exhausted; every
+// wave leaves the loop once the counter passes n.  A barrier follows every
+// task (the next one reuses LDS).
+
+__device__ __forceinline__ int claim_task(int *counter)
+{
+    __shared__ int s_task;
+    if (threadIdx.x == 0) s_task = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = s_task;
+    __syncthreads();
+    return t;
+}
+
+template <int MAXV>
+__global__ void __launch_bounds__(1024)
+    k_batch_forward(const FwdParams *items, const BatchTask *tasks, int n, int *counter)
+{
+    for (;;) {
+        const int t = claim_task(counter);
+        if (t >= n) break;
+        const BatchTask tk = tasks[t];
+        forward_task<MAXV>(items[tk.item], tk.a);
+        __syncthreads();
+    }
+}
+
+template <int MAXV>
+__global__ void __launch_bounds__(1024)
+    k_batch_main(const MainParams *items, const BatchTask *tasks, int n, int *counter)
+{
+    for (;;) {
+        const int t = claim_task(counter);
+        if (t >= n) break;
+        const BatchTask tk = tasks[t];
+        const MainParams &p = items[tk.item];
+        switch (p.out_mode) {
+        case kOutComplex: main_task<MAXV, kOutComplex>(p, tk.a, tk.b); break;
+        case kOutPower: main_task<MAXV, kOutPower>(p, tk.a, tk.b); break;
+        default: main_task<MAXV, kOutBand>(p, tk.a, tk.b); break;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_zero_counters(int *c, int n)
+{
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+}
+
+hipError_t launch_zero_counters(int *c, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, c, n);
+    return hipGetLastError();
+}
+
+template <class K>
+static int occupancy_grid(K kernel, int threads, size_t lds, int n_tasks)
+{
+    int dev = 0, cus = 256, per_cu = 1;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const int g = cus * per_cu;
+    return n_tasks < g ? n_tasks : g;
+}
+
+hipError_t launch_batch_forward(const FwdParams *items, const BatchTask *tasks, int n,
+                                int *counter, int threads, int maxv, size_t lds, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    if (maxv <= 16) {
+        set_lds_limit((const void *)k_batch_forward<16>, lds);
+        const int g = occupancy_grid(k_batch_forward<16>, threads, lds, n);
+        hipLaunchKernelGGL(k_batch_forward<16>, dim3(g), dim3(threads), lds, s, items, tasks, n,
+                           counter);
+    } else {
+        set_lds_limit((const void *)k_batch_forward<24>, lds);
+        const int g = occupancy_grid(k_batch_forward<24>, threads, lds, n);
+        hipLaunchKernelGGL(k_batch_forward<24>, dim3(g), dim3(threads), lds, s, items, tasks, n,
+                           counter);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_main(const MainParams *items, const BatchTask *tasks, int n,
+                             int *counter, int threads, int maxv, size_t lds, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    if (maxv <= 16) {
+        set_lds_limit((const void *)k_batch_main<16>, lds);
+        const int g = occupancy_grid(k_batch_main<16>, threads, lds, n);
+        hipLaunchKernelGGL(k_batch_main<16>, dim3(g), dim3(threads), lds, s, items, tasks, n,
+                           counter);
+    } else {
+        set_lds_limit((const void *)k_batch_main<24>, lds);
+        const int g = occupancy_grid(k_batch_main<24>, threads, lds, n);
+        hipLaunchKernelGGL(k_batch_main<24>, dim3(g), dim3(threads), lds, s, items, tasks, n,
+                           counter);
+    }
+    return hipGetLastError();
 }
 
 template <int MAXV, int MODE>

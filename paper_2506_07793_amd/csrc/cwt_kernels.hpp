@@ -56,6 +56,22 @@ struct MainParams {
     int variant;           // register-resident kernel: 0 table twiddles, 1 power twiddles
 };
 
+// ------------------------------------------------------------- batched --
+// One task of a persistent batch kernel: item index and its channel pair
+// (forward) or (channel, output row) (transform).
+struct BatchTask {
+    int item;
+    int a;
+    int b;
+    int cost;  // sort key (larger first)
+};
+
+hipError_t launch_zero_counters(int *c, int n, hipStream_t s);
+hipError_t launch_batch_forward(const FwdParams *items, const BatchTask *tasks, int n,
+                                int *counter, int threads, int maxv, size_t lds, hipStream_t s);
+hipError_t launch_batch_main(const MainParams *items, const BatchTask *tasks, int n,
+                             int *counter, int threads, int maxv, size_t lds, hipStream_t s);
+
 // ----------------------------------------------------------- streaming --
 // One completed hop of one session.
 struct StreamJob {
