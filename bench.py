@@ -38,12 +38,76 @@ def parse():
                     help="channels of the oracle's timed sample (all 100 frequencies each)")
     ap.add_argument("--graph", type=int, default=0,
                     help="1: replay the step as a captured HIP graph; 0: direct launches (default)")
+    ap.add_argument("--batch-steps", type=int, default=3,
+                    help="timed steps of the config-3 batch run (0 skips it)")
     ap.add_argument("--stream-seconds", type=float, default=6.0,
                     help="real-time length of each streaming run (0 skips the streaming runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (scales the HBM "
                          "byte counters of a profiler run)")
     return ap.parse_args()
+
+
+def bench_batch(steps, n_rec=256):
+    """Config-3 batch: 256 seeded recordings (lengths 500-20000, 1-128 channels,
+    20-150 log frequencies 0.5 Hz-min(200, 0.45 sfreq), sfreq in {250, 500, 1000,
+    2048}), power output, FP32.  One graph launch of the persistent kernels per
+    step, against the sum of per-recording cwt_execute calls on the same data.
+    Inputs are device normal noise at EEG scale (the timings do not depend on
+    the values; the parity tests use the structured EEG generator)."""
+    import torch
+
+    import paper_2506_07793_amd as cwt
+    import synth
+
+    recs = synth.batch_recordings()[:n_rec]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4)
+    items, plans = [], []
+    pts = 0
+    out_bytes = 0
+    in_bytes = 0
+    for r in recs:
+        plan = cwt.Plan(r["N"], r["sfreq"], r["freqs"], n_cycles=r["n_cycles"], out="power")
+        x = torch.randn(r["C"], r["N"], device="cuda", generator=g) * 20.0
+        out = plan.alloc_output(r["C"])
+        items.append((plan, x, out))
+        plans.append(plan)
+        pts += r["C"] * r["F"] * r["N"]
+        out_bytes += out.numel() * 4
+        in_bytes += x.numel() * 4 + r["C"] * (plan.L // 2 + 1) * 8 * 2
+    batch = cwt.Batch(items)
+    ws = batch.alloc_workspace()
+    wss = [p.alloc_workspace(x.shape[0]) for p, x, _ in items]
+    stream = torch.cuda.current_stream()
+    batch.execute(ws)
+    for (p, x, o), w in zip(items, wss):
+        p.execute(x, out=o, ws=w)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        batch.execute(ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1) / steps
+    e0.record(stream)
+    for _ in range(steps):
+        for (p, x, o), w in zip(items, wss):
+            p.execute(x, out=o, ws=w)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_loop = e0.elapsed_time(e1) / steps
+    res = {"workload": "%d recordings (config-3 draw), power out" % len(recs),
+           "points": pts, "out_GB": out_bytes / 1e9,
+           "batch_graph_ms": ms_batch, "batch_pts_per_s": pts / (ms_batch * 1e-3),
+           "per_recording_ms": ms_loop, "per_recording_pts_per_s": pts / (ms_loop * 1e-3),
+           "batch_hbm_frac": (out_bytes + in_bytes) / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    del items, batch, ws, wss
+    for p in plans:
+        p.close()
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_stream(n_sessions, C, sfreq, win_s, hop_s, seconds, seed, max_batch, deadline_us):
@@ -279,6 +343,33 @@ def main():
                           "GBps": out.numel() * out.element_size() / (ms_fill * 1e-3) / 1e9,
                           "ms": ms_fill},
     }
+
+    # Config-2 precision variants: the same workload through the split-precision
+    # DFT-as-GEMM (MFMA) transform kernel.  Their errors against the FP64
+    # oracle are measured by tests/test_gpu_split.py.
+    prec_runs = []
+    for prec in ("split_f16", "split_bf16"):
+        pp = cwt.Plan(N, cfg["sfreq"], cfg["freqs"], n_cycles=cfg["n_cycles"], out=args.out,
+                      precision=prec)
+        with torch.cuda.stream(stream):
+            pp.forward_spectra(x, ws, stream=stream)
+            for _ in range(3):
+                pp.transform_spectra(C, out, ws, stream=stream)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            for _ in range(K):
+                pp.transform_spectra(C, out, ws, stream=stream)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+        ms_p = ev0.elapsed_time(ev1) / K
+        prec_runs.append({"precision": prec, "transform_ms": ms_p,
+                          "transform_pts_per_s": pts / (ms_p * 1e-3),
+                          "hbm_frac": main_bytes / (ms_p * 1e-3) / 1e9 / HBM_PEAK_GBS})
+        pp.close()
+    result["precision_variants"] = prec_runs
+
+    if args.batch_steps > 0:
+        result["batch"] = bench_batch(args.batch_steps)
 
     if args.stream_seconds > 0:
         result["stream"] = [

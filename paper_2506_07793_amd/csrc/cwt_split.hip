@@ -1,21 +1,288 @@
-// Split-precision (hi + lo) DFT-as-GEMM path on MFMA.  Not built yet: plans
-// asking for it are refused with CWT_E_UNSUPPORTED.
+// Split-precision DFT-as-GEMM path on MFMA (gfx950), padded length 4096.
+//
+// The inverse transform runs as three radix-16 Stockham stages.  Each stage's
+// 16-point complex DFTs are one real GEMM per 16 butterflies:
+//   [Yr; Yi] = [[Fr, -Fi], [Fi, Fr]] [Xr; Xi],  F[k][r] = exp(+2 pi i k r / 16),
+// on v_mfma_f32_16x16x32_{f16,bf16} (M = 16 outputs, K = 32 = re and im of
+// the 16 inputs, N = 16 butterflies).  Operands are split into a high and a
+// low half-precision part (x = hi + lo) and the product is formed from three
+// MFMAs, hi*hi + hi*lo + lo*hi, accumulated in FP32.  For FP16 every
+// butterfly's inputs are scaled by a power of two that puts their largest
+// magnitude in [2^14, 2^15) (FP16 range; undone exactly after the MFMA); BF16
+// keeps FP32's exponent range and is not scaled.  Twiddles are applied in
+// FP32 on the VALU when a stage stores its outputs; the DFT constants and
+// twiddles are FP64 values rounded once.  The forward transform of the
+// channels is the FP32 path's.
 #include "cwt_internal.hpp"
+#include "fft_core.hpp"
+
+using namespace cwtk;
+
+namespace {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kL = 4096;
+constexpr int kT = 256;
+
+template <int PREC>
+struct SplitOps;
+
+template <>
+struct SplitOps<CWT_PREC_SPLIT_F16> {
+    typedef h8 vec;
+    typedef _Float16 scalar;
+    static __device__ __forceinline__ void split(float v, _Float16 &hi, _Float16 &lo)
+    {
+        hi = (_Float16)v;
+        lo = (_Float16)(v - (float)hi);
+    }
+    static __device__ __forceinline__ f4 mfma(vec a, vec b, f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+    static constexpr bool kScale = true;
+};
+
+template <>
+struct SplitOps<CWT_PREC_SPLIT_BF16> {
+    typedef b8 vec;
+    typedef __bf16 scalar;
+    static __device__ __forceinline__ void split(float v, __bf16 &hi, __bf16 &lo)
+    {
+        hi = (__bf16)v;
+        lo = (__bf16)(v - (float)hi);
+    }
+    static __device__ __forceinline__ f4 mfma(vec a, vec b, f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    static constexpr bool kScale = false;
+};
+
+// Largest power-of-two exponent e with max * 2^e < 2^15 (0 when max is 0).
+__device__ __forceinline__ int fp16_exponent(float m)
+{
+    if (!(m > 0.f)) return 0;
+    return 14 - ilogbf(m);
+}
+
+}  // namespace
+
+template <int MODE, int PREC>
+__global__ void __launch_bounds__(kT) k_split_main(MainParams p)
+{
+    typedef SplitOps<PREC> Ops;
+    typedef typename Ops::vec vec;
+    typedef typename Ops::scalar sc;
+    __shared__ cf lds[kL];
+    float *ldsf = reinterpret_cast<float *>(lds);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int n = lane & 15, q = lane >> 4;
+    const int N = p.N;
+    const cf *tw = reinterpret_cast<const cf *>(p.tw);
+
+    // DFT operands of this lane: row m = n, columns k = 8 q + i.
+    vec ar_hi, ar_lo, ai_hi, ai_lo;
+    for (int i = 0; i < 8; ++i) {
+        const int k = 8 * q + i;
+        const int r = k & 15;
+        double sn, cs;
+        sincospi(2.0 * (double)((n * r) & 15) / 16.0, &sn, &cs);
+        // columns 0..15 multiply Xr, 16..31 multiply Xi
+        const float fr = (k < 16) ? (float)cs : (float)(-sn);
+        const float fi = (k < 16) ? (float)sn : (float)cs;
+        sc h, l;
+        Ops::split(fr, h, l);
+        ar_hi[i] = h;
+        ar_lo[i] = l;
+        Ops::split(fi, h, l);
+        ai_hi[i] = h;
+        ai_lo[i] = l;
+    }
+
+    const int c = blockIdx.x / p.n_rows;
+    const int row = blockIdx.x - c * p.n_rows;
+    int qb, qe;
+    if (MODE == kOutBand) {
+        qb = p.grp_off[row];
+        qe = p.grp_off[row + 1];
+    } else {
+        qb = row;
+        qe = row + 1;
+    }
+    const cf *X = reinterpret_cast<const cf *>(p.Xh) + (int64_t)c * p.Lh;
+    float *orow_band = reinterpret_cast<float *>(p.out) + ((int64_t)c * p.n_rows + row) * N;
+    const float inv_n = 1.0f / (float)(qe - qb);
+
+    for (int qq = qb; qq < qe; ++qq) {
+        const int f = (MODE == kOutBand) ? p.grp_freq[qq] : qq;
+        const BandDesc bd = p.band[f];
+        const float *Hf = p.H + bd.off;
+        const int K = bd.K;
+        const int lo_u = bd.lo < 0 ? bd.lo + kL : bd.lo;
+        float2 *ocx = reinterpret_cast<float2 *>(p.out) + ((int64_t)c * p.n_rows + f) * N;
+        float *opw = reinterpret_cast<float *>(p.out) + ((int64_t)c * p.n_rows + f) * N;
+        const bool first = (qq == qb), final_f = (qq == qe - 1);
+        if (qq != qb) __syncthreads();
+
+        int Ns = 1;
+        for (int s = 0; s < 3; ++s) {
+            f4 dr[4], di[4];
+            int ex[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int j = 64 * wave + 16 * g + n;
+                float v[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int r = 8 * (q & 1) + i;
+                    const int idx = j + 256 * r;  // Stockham input element (j, r)
+                    if (s == 0) {
+                        const int o = (idx - lo_u) & (kL - 1);
+                        float val = 0.f;
+                        if (o < K) {
+                            const bool upper = idx > kL / 2;
+                            const cf xv = X[upper ? kL - idx : idx];
+                            const float part = (q >> 1) ? (upper ? -xv.y : xv.y) : xv.x;
+                            val = part * Hf[o];
+                        }
+                        v[i] = val;
+                    } else {
+                        v[i] = ldsf[2 * idx + (q >> 1)];
+                    }
+                }
+                int e = 0;
+                if (Ops::kScale) {
+                    float m = 0.f;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(v[i]));
+                    m = fmaxf(m, __shfl_xor(m, 16));
+                    m = fmaxf(m, __shfl_xor(m, 32));
+                    e = fp16_exponent(m);
+                }
+                vec bh, bl;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    sc h, l;
+                    Ops::split(ldexpf(v[i], e), h, l);
+                    bh[i] = h;
+                    bl[i] = l;
+                }
+                f4 zr = {0.f, 0.f, 0.f, 0.f}, zi = {0.f, 0.f, 0.f, 0.f};
+                zr = Ops::mfma(ar_hi, bh, zr);
+                zr = Ops::mfma(ar_hi, bl, zr);
+                zr = Ops::mfma(ar_lo, bh, zr);
+                zi = Ops::mfma(ai_hi, bh, zi);
+                zi = Ops::mfma(ai_hi, bl, zi);
+                zi = Ops::mfma(ai_lo, bh, zi);
+                dr[g] = zr;
+                di[g] = zi;
+                ex[g] = e;
+            }
+            __syncthreads();  // every wave has read this stage's inputs
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int j = 64 * wave + 16 * g + n;
+                const int jm = j & (Ns - 1);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = 4 * q + i;
+                    cf y = mk(ldexpf(dr[g][i], -ex[g]), ldexpf(di[g][i], -ex[g]));
+                    const int d = (j - jm) * 16 + jm + k * Ns;  // Stockham output slot
+                    if (s < 2) {
+                        // next stage's twiddle on its input element (d mod 256, d / 256)
+                        const int Nn = Ns * 16;
+                        const int jn = d & 255, rn = d >> 8;
+                        y = mul(y, tw[(jn & (Nn - 1)) * rn * (kL / (Nn * 16))]);
+                        lds[d] = y;
+                    } else if (d < N) {
+                        const float pw = y.x * y.x + y.y * y.y;
+                        if (MODE == kOutComplex) {
+                            ocx[d] = make_float2(y.x, y.y);
+                        } else if (MODE == kOutPower) {
+                            opw[d] = pw;
+                        } else {
+                            const float a = first ? pw : orow_band[d] + pw;
+                            orow_band[d] = final_f ? a * inv_n : a;
+                        }
+                    }
+                }
+            }
+            if (s < 2) __syncthreads();
+            Ns *= 16;
+        }
+    }
+}
 
 namespace cwtrt {
 
-bool split_precision_available() { return false; }
-int prepare_split_precision(cwt_plan &, hipStream_t) { return CWT_E_UNSUPPORTED; }
-void release_split_precision(cwt_plan &) {}
-size_t split_workspace_bytes(const cwt_plan &, int64_t) { return 0; }
-int enqueue_execute_split(const cwt_plan &, const float *, int64_t, int64_t, void *, void *,
-                          hipStream_t)
+bool split_precision_available() { return true; }
+
+int prepare_split_precision(cwt_plan &P, hipStream_t)
 {
-    return CWT_E_UNSUPPORTED;
+    if (P.L != kL)
+        return fail(CWT_E_UNSUPPORTED,
+                    "split-precision MFMA path is built for padded length %d (plan has %d)", kL,
+                    P.L);
+    return CWT_OK;
 }
-int enqueue_transform_split(const cwt_plan &, int64_t, void *, void *, hipStream_t)
+
+void release_split_precision(cwt_plan &) {}
+
+size_t split_workspace_bytes(const cwt_plan &, int64_t) { return 0; }
+
+template <int MODE, int PREC>
+static hipError_t launch_split_t(const MainParams &mp, hipStream_t s)
 {
-    return CWT_E_UNSUPPORTED;
+    hipLaunchKernelGGL((k_split_main<MODE, PREC>), dim3(mp.C * mp.n_rows), dim3(kT), 0, s, mp);
+    return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_split_modes(const MainParams &mp, hipStream_t s)
+{
+    switch (mp.out_mode) {
+    case kOutComplex: return launch_split_t<kOutComplex, PREC>(mp, s);
+    case kOutPower: return launch_split_t<kOutPower, PREC>(mp, s);
+    default: return launch_split_t<kOutBand, PREC>(mp, s);
+    }
+}
+
+int enqueue_transform_split(const cwt_plan &P, int64_t C, void *out, void *ws, hipStream_t s)
+{
+    if (C == 0) return CWT_OK;
+    MainParams mp{};
+    mp.Xh = reinterpret_cast<const float2 *>(ws);
+    mp.Lh = P.L / 2 + 1;
+    mp.H = P.d_H;
+    mp.band = P.d_band;
+    mp.tw = P.d_tw;
+    mp.out = out;
+    mp.out_mode = P.opts.out;
+    mp.N = (int)P.n;
+    mp.F = P.F;
+    mp.C = (int)C;
+    mp.n_rows = (P.opts.out == CWT_OUT_BANDPOWER_F32) ? P.n_bands : P.F;
+    mp.grp_freq = P.d_grp_freq;
+    mp.grp_off = P.d_grp_off;
+    mp.rp = P.rp;
+    hipError_t e = (P.opts.precision == CWT_PREC_SPLIT_F16)
+                       ? launch_split_modes<CWT_PREC_SPLIT_F16>(mp, s)
+                       : launch_split_modes<CWT_PREC_SPLIT_BF16>(mp, s);
+    if (e != hipSuccess) return hip_fail(e, "split-precision transform launch");
+    return CWT_OK;
+}
+
+int enqueue_execute_split(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride,
+                          void *out, void *ws, hipStream_t s)
+{
+    int rc = enqueue_forward(P, x, C, x_stride, ws, s);
+    if (rc != CWT_OK) return rc;
+    return enqueue_transform_split(P, C, out, ws, s);
 }
 
 }  // namespace cwtrt

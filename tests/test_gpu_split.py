@@ -1,0 +1,79 @@
+"""Split-precision DFT-as-GEMM (MFMA) path: error against the FP64 oracle,
+reported for every output kind, and compared with the FP32 path.
+
+The bound asserted here is the reporting bar of this variant, not the FP32
+gate: FP16 hi+lo splitting carries about 22 significant bits, BF16 hi+lo
+about 16, so e_P <= 1e-5 (FP16) and <= 1e-4 (BF16)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2506_07793_amd as cwt
+from paper_2506_07793_amd import _lib
+import synth
+
+pytestmark = pytest.mark.gpu
+BOUND = {"split_f16": 1e-5, "split_bf16": 1e-4}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    yield
+
+
+@pytest.fixture(scope="module")
+def data():
+    d = synth.config1(C=2)
+    x = d["x"]
+    ref = oracle.cwt(x.astype(np.float64), d["sfreq"], d["freqs"], d["n_cycles"])
+    return d, ref
+
+
+@pytest.mark.parametrize("prec", ["split_f16", "split_bf16"])
+def test_split_complex_and_power(prec, data):
+    d, ref = data
+    xt = torch.from_numpy(d["x"]).cuda()
+    res = {}
+    for out in ("complex64", "power", "bandpower"):
+        plan = cwt.Plan(4096, d["sfreq"], d["freqs"], n_cycles=d["n_cycles"], out=out,
+                        precision=prec)
+        got = plan.execute(xt).cpu().numpy()
+        torch.cuda.synchronize()
+        if out == "complex64":
+            e_P, e_W = oracle.parity_errors(got, ref)
+            res[out] = (e_P, e_W)
+        else:
+            P = oracle.power(ref)
+            if out == "bandpower":
+                P = oracle.band_power(P, oracle.band_groups(d["freqs"]))
+            e_P = float(np.max(np.abs(got - P)) / P.max())
+            res[out] = (e_P, None)
+        plan.close()
+    print("%s: complex e_P=%.3e e_W=%.3e | power e_P=%.3e | bandpower e=%.3e" % (
+        prec, res["complex64"][0], res["complex64"][1], res["power"][0], res["bandpower"][0]))
+    for out, (e_P, _) in res.items():
+        assert e_P <= BOUND[prec], (out, e_P)
+
+
+def test_split_full_size_sampled_rows():
+    d = synth.config1(C=64)
+    xt = torch.from_numpy(d["x"]).cuda()
+    rng = np.random.default_rng(12)
+    rows = np.stack([rng.integers(0, 64, 16), rng.integers(0, 100, 16)], axis=1)
+    ref = oracle.cwt(d["x"].astype(np.float64), d["sfreq"], d["freqs"], d["n_cycles"], rows=rows)
+    for prec in ("split_f16", "split_bf16"):
+        plan = cwt.Plan(4096, d["sfreq"], d["freqs"], n_cycles=d["n_cycles"], precision=prec)
+        W = plan.execute(xt).cpu().numpy()
+        e_P, e_W = oracle.parity_errors(W[rows[:, 0], rows[:, 1]], ref)
+        print("%s 64ch sampled: e_P=%.3e e_W=%.3e" % (prec, e_P, e_W))
+        assert e_P <= BOUND[prec]
+        plan.close()
+
+
+def test_split_needs_length_4096():
+    with pytest.raises(cwt.CwtError) as ei:
+        cwt.Plan(1000, 1000.0, [10.0, 20.0], n_cycles=5.0, precision="split_f16")
+    assert ei.value.code == _lib.CWT_E_UNSUPPORTED
