@@ -39,7 +39,7 @@ def parse():
     ap.add_argument("--graph", type=int, default=0,
                     help="1: replay the step as a captured HIP graph; 0: direct launches (default)")
     ap.add_argument("--batch-steps", type=int, default=3,
-                    help="timed steps of the config-3 batch run (0 skips it)")
+                    help="timed steps of the 256-recording batch run (0 skips it)")
     ap.add_argument("--stream-seconds", type=float, default=6.0,
                     help="real-time length of each streaming run (0 skips the streaming runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -98,7 +98,7 @@ def bench_batch(steps, n_rec=256):
     e1.record(stream)
     torch.cuda.synchronize()
     ms_loop = e0.elapsed_time(e1) / steps
-    res = {"workload": "%d recordings (config-3 draw), power out" % len(recs),
+    res = {"workload": "%d seeded heterogeneous recordings, power out" % len(recs),
            "points": pts, "out_GB": out_bytes / 1e9,
            "batch_graph_ms": ms_batch, "batch_pts_per_s": pts / (ms_batch * 1e-3),
            "per_recording_ms": ms_loop, "per_recording_pts_per_s": pts / (ms_loop * 1e-3),
@@ -240,7 +240,7 @@ def main():
         print(json.dumps({"copy_bytes": a.numel() * 4, "copies": 3}), flush=True)
         return
     C, N, F = 64, 4096, 100
-    cfg = synth.config1(seed=2, C=C, N=N, F=F)
+    cfg = synth.eeg_64ch(seed=2, C=C, N=N, F=F)
     x = torch.from_numpy(cfg["x"]).to(dev)
     plan = cwt.Plan(N, cfg["sfreq"], cfg["freqs"], n_cycles=cfg["n_cycles"], out=args.out)
     out = plan.alloc_output(C, device=dev)

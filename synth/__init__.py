@@ -27,7 +27,7 @@ def tones(n, sfreq, comps, noise_sd=0.0, seed=None):
     return x
 
 
-def config0_signal(seed=1):
+def two_tone_signal(seed=1):
     """1 channel, 1000 samples at 1000 Hz: sin 10 Hz + 0.5 sin 40 Hz + N(0, 0.5^2)."""
     return tones(1000, 1000.0, [(10.0, 1.0), (40.0, 0.5)], noise_sd=0.5, seed=seed)[None, :]
 
@@ -77,8 +77,8 @@ def eeg_cycles(freqs):
     return np.clip(np.asarray(freqs, dtype=np.float64) / 2.0, 3.0, 10.0)
 
 
-def config1(seed=2, C=64, N=4096, F=100):
-    """64 ch x 4096 samples at 1000 Hz; 100 log-spaced freqs 1-100 Hz."""
+def eeg_64ch(seed=2, C=64, N=4096, F=100):
+    """64 ch x 4096 samples at 1000 Hz; 100 log-spaced freqs 1-100 Hz (seed 2)."""
     sfreq = 1000.0
     freqs = log_freqs(1.0, 100.0, F)
     return dict(x=eeg(C, N, sfreq, seed), sfreq=sfreq, freqs=freqs, n_cycles=eeg_cycles(freqs))

@@ -48,7 +48,7 @@ def _desc(**kw):
     return cwt.describe(**args)
 
 
-def test_describe_config1():
+def test_describe_eeg():
     d = _desc()
     assert d.L == 4096 and d.n_freqs == 100 and d.out_rows == 100 and d.out_elem_bytes == 8
     radix = [d.radix[i] for i in range(d.n_passes)]

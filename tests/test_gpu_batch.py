@@ -103,8 +103,8 @@ def test_graph_replays_with_new_inputs():
         it["plan"].close()
 
 
-def test_config3_draw_subset():
-    """First recordings of the seeded config-3 draw (lengths 500-20000, 1-128
+def test_seeded_recording_draw_subset():
+    """First recordings of the seeded heterogeneous draw (lengths 500-20000, 1-128
     channels, 20-150 frequencies, four sampling rates), power output."""
     recs = synth.batch_recordings()[:12]
     its = []

@@ -71,32 +71,32 @@ def test_tables_within_one_ulp_of_fp64(n, sfreq, F, wavelet):
     plan.close()
 
 
-# ------------------------------------------------------------ config 0 --
+# ------------------------------------------- two tones, 1 ch x 1000 --
 
 @pytest.mark.parametrize("pad,L", [("smooth7", 1000), ("pow2", 1024)])
-def test_config0_single_channel(pad, L):
+def test_two_tone_single_channel(pad, L):
     """1 ch x 1000 samples at 1000 Hz, Morlet sigma 7, 50 freqs 1-50 Hz."""
-    x = synth.config0_signal().astype(np.float32)
+    x = synth.two_tone_signal().astype(np.float32)
     freqs = np.arange(1.0, 51.0)
     plan, W = _run(x, 1000.0, freqs, 7.0, pad=pad)
     assert plan.L == L
     ref = oracle.cwt(x.astype(np.float64), 1000.0, freqs, 7.0, L=L)
-    _parity(W, ref, "config0 " + pad)
+    _parity(W, ref, "two-tone " + pad)
     plan.close()
 
 
-# ------------------------------------------------------------ config 1 --
+# ----------------------------------------- EEG 64 ch x 4096, 100 freqs --
 
-def _config1(C):
-    d = synth.config1(C=C)
+def _eeg(C):
+    d = synth.eeg_64ch(C=C)
     return d["x"], d["sfreq"], d["freqs"], d["n_cycles"]
 
 
-def test_config1_full_oracle_two_channels():
-    x, sfreq, freqs, cyc = _config1(2)
+def test_eeg_full_oracle_two_channels():
+    x, sfreq, freqs, cyc = _eeg(2)
     plan, W = _run(x, sfreq, freqs, cyc)
     ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc)
-    _parity(W, ref, "config1 C=2 full")
+    _parity(W, ref, "eeg C=2 full")
     # per-row worst (each (c, f) row relative to its own peak power)
     Pg, Pr = oracle.power(W), oracle.power(ref)
     row = np.max(np.abs(Pg - Pr), axis=2) / np.max(Pr, axis=2)
@@ -105,9 +105,9 @@ def test_config1_full_oracle_two_channels():
     plan.close()
 
 
-def test_config1_full_size_sampled_rows():
+def test_eeg_full_size_sampled_rows():
     """64 ch x 4096 x 100 freqs (the benchmarked shape), oracle on sampled rows."""
-    x, sfreq, freqs, cyc = _config1(64)
+    x, sfreq, freqs, cyc = _eeg(64)
     plan, W = _run(x, sfreq, freqs, cyc)
     assert W.shape == (64, 100, 4096)
     rng = np.random.default_rng(11)
@@ -116,12 +116,12 @@ def test_config1_full_size_sampled_rows():
     rows[1] = (63, 99)
     ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc, rows=rows)
     got = W[rows[:, 0], rows[:, 1]]
-    _parity(got, ref, "config1 64ch sampled")
+    _parity(got, ref, "eeg 64ch sampled")
     plan.close()
 
 
-def test_config1_power_and_bandpower():
-    x, sfreq, freqs, cyc = _config1(3)
+def test_eeg_power_and_bandpower():
+    x, sfreq, freqs, cyc = _eeg(3)
     ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc)
     Pr = oracle.power(ref)
     plan, P = _run(x, sfreq, freqs, cyc, out="power")
@@ -192,7 +192,7 @@ def test_tiny_lengths_gabor(n):
 
 def test_stages_equal_execute():
     """cwt_forward_spectra + cwt_transform_spectra == cwt_execute, bitwise."""
-    x, sfreq, freqs, cyc = _config1(5)
+    x, sfreq, freqs, cyc = _eeg(5)
     plan = cwt.Plan(4096, sfreq, freqs, n_cycles=cyc)
     xt = torch.from_numpy(x).cuda()
     a = plan.execute(xt)
@@ -233,7 +233,7 @@ def test_gabor_and_near_nyquist():
 
 
 def test_zero_channels_is_noop_and_determinism():
-    x, sfreq, freqs, cyc = _config1(4)
+    x, sfreq, freqs, cyc = _eeg(4)
     plan = cwt.Plan(4096, sfreq, freqs, n_cycles=cyc)
     xt = torch.from_numpy(x).cuda()
     out = plan.alloc_output(4)
@@ -256,7 +256,7 @@ def test_zero_channels_is_noop_and_determinism():
 
 
 def test_two_streams_concurrently():
-    x, sfreq, freqs, cyc = _config1(8)
+    x, sfreq, freqs, cyc = _eeg(8)
     plan = cwt.Plan(4096, sfreq, freqs, n_cycles=cyc, out="power")
     xt = torch.from_numpy(x).cuda()
     ref = plan.execute(xt).clone()
@@ -276,7 +276,7 @@ def test_two_streams_concurrently():
 def test_fixed_and_generic_kernels_agree(out, monkeypatch):
     """The register-resident kernel (L = 4096) and the generic kernel both
     match the oracle, and each other to FP32 rounding."""
-    x, sfreq, freqs, cyc = _config1(2)
+    x, sfreq, freqs, cyc = _eeg(2)
     xt = torch.from_numpy(x).cuda()
     monkeypatch.setenv("CWT_GENERIC_ONLY", "1")
     pg = cwt.Plan(4096, sfreq, freqs, n_cycles=cyc, out=out)

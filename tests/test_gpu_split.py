@@ -26,7 +26,7 @@ def _gpu():
 
 @pytest.fixture(scope="module")
 def data():
-    d = synth.config1(C=2)
+    d = synth.eeg_64ch(C=2)
     x = d["x"]
     ref = oracle.cwt(x.astype(np.float64), d["sfreq"], d["freqs"], d["n_cycles"])
     return d, ref
@@ -59,7 +59,7 @@ def test_split_complex_and_power(prec, data):
 
 
 def test_split_full_size_sampled_rows():
-    d = synth.config1(C=64)
+    d = synth.eeg_64ch(C=64)
     xt = torch.from_numpy(d["x"]).cuda()
     rng = np.random.default_rng(12)
     rows = np.stack([rng.integers(0, 64, 16), rng.integers(0, 100, 16)], axis=1)

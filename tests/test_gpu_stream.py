@@ -105,7 +105,7 @@ def test_many_sessions_batched():
 
 
 @pytest.mark.parametrize("W,hop,sfreq,C,F", [(2000, 50, 1000.0, 64, 40), (4096, 102, 2048.0, 256, 40)])
-def test_config4_shapes(W, hop, sfreq, C, F):
+def test_serving_shapes(W, hop, sfreq, C, F):
     """Serving shapes: 64 ch x 2 s at 1000 Hz (hop 50) and 256 ch x 2 s at 2048 Hz (hop 102)."""
     plan, freqs, cyc = _plan(W, sfreq, F, 100.0)
     srv = Server(8 << 30, max_batch=4, deadline_us=500)

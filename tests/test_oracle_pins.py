@@ -239,9 +239,9 @@ def test_sinusoid_peak_amplitude_and_argmax(orc):
     assert freqs[29 + np.argmax(P[29:])] == 40.0
 
 
-def test_config0_noisy_signal_peaks(orc):
-    """Config 0 (sin 10 + 0.5 sin 40 + noise 0.5, seeded): power peaks near the tones."""
-    x = synth.config0_signal()
+def test_two_tone_noisy_signal_peaks(orc):
+    """Two tones (sin 10 + 0.5 sin 40 + noise 0.5, seeded): power peaks near the tones."""
+    x = synth.two_tone_signal()
     freqs = np.arange(1.0, 51.0)
     P = orc.power(orc.cwt(x, 1000.0, freqs, 7.0)[0]).mean(axis=1)
     assert abs(freqs[np.argmax(P[:25])] - 10.0) <= 1.0
@@ -328,13 +328,13 @@ def test_band_power_is_mean_of_power(orc):
 
 # --------------------------------------------------------------- fixtures --
 
-def test_config0_golden_samples(orc):
+def test_two_tone_golden_samples(orc):
     """Regression guard: the oracle reproduces the samples make_golden.py stored."""
     import os
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
-                        "config0_oracle_samples.txt")
+                        "two_tone_oracle_samples.txt")
     rows = np.loadtxt(path)
-    W = orc.cwt(synth.config0_signal(), 1000.0, np.arange(1.0, 51.0), 7.0)[0]
+    W = orc.cwt(synth.two_tone_signal(), 1000.0, np.arange(1.0, 51.0), 7.0)[0]
     for fi, t, re, im in rows:
         w = W[int(fi), int(t)]
         assert abs(w.real - re) <= 1e-13 * max(1.0, abs(re))
