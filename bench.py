@@ -67,15 +67,35 @@ def bench_batch(steps, n_rec=256):
     pts = 0
     out_bytes = 0
     in_bytes = 0
-    for r in recs:
-        plan = cwt.Plan(r["N"], r["sfreq"], r["freqs"], n_cycles=r["n_cycles"], out="power")
-        x = torch.randn(r["C"], r["N"], device="cuda", generator=g) * 20.0
-        out = plan.alloc_output(r["C"])
-        items.append((plan, x, out))
-        plans.append(plan)
-        pts += r["C"] * r["F"] * r["N"]
-        out_bytes += out.numel() * 4
-        in_bytes += x.numel() * 4 + r["C"] * (plan.L // 2 + 1) * 8 * 2
+    # Autotune the first plan of each padded length (on up to 16 channels);
+    # later plans of that length take the choice from the tuning cache file.
+    import tempfile
+    tune_file = tempfile.NamedTemporaryFile(prefix="cwt_tune_", suffix=".txt", delete=False)
+    tune_file.close()
+    old_cache = os.environ.get("CWT_AUTOTUNE_CACHE")
+    os.environ["CWT_AUTOTUNE_CACHE"] = tune_file.name
+    tuned = {}
+    t_tune = 0.0
+    try:
+        for r in recs:
+            plan = cwt.Plan(r["N"], r["sfreq"], r["freqs"], n_cycles=r["n_cycles"], out="power")
+            if plan.L not in tuned:
+                t0 = time.perf_counter()
+                tuned[plan.L] = plan.autotune(r["C"])
+                t_tune += time.perf_counter() - t0
+            x = torch.randn(r["C"], r["N"], device="cuda", generator=g) * 20.0
+            out = plan.alloc_output(r["C"])
+            items.append((plan, x, out))
+            plans.append(plan)
+            pts += r["C"] * r["F"] * r["N"]
+            out_bytes += out.numel() * 4
+            in_bytes += x.numel() * 4 + r["C"] * (plan.L // 2 + 1) * 8 * 2
+    finally:
+        if old_cache is None:
+            os.environ.pop("CWT_AUTOTUNE_CACHE", None)
+        else:
+            os.environ["CWT_AUTOTUNE_CACHE"] = old_cache
+        os.unlink(tune_file.name)
     batch = cwt.Batch(items)
     ws = batch.alloc_workspace()
     wss = [p.alloc_workspace(x.shape[0]) for p, x, _ in items]
@@ -99,6 +119,7 @@ def bench_batch(steps, n_rec=256):
     torch.cuda.synchronize()
     ms_loop = e0.elapsed_time(e1) / steps
     res = {"workload": "%d seeded heterogeneous recordings, power out" % len(recs),
+           "autotune_s": t_tune, "distinct_lengths": len(tuned),
            "points": pts, "out_GB": out_bytes / 1e9,
            "batch_graph_ms": ms_batch, "batch_pts_per_s": pts / (ms_batch * 1e-3),
            "per_recording_ms": ms_loop, "per_recording_pts_per_s": pts / (ms_loop * 1e-3),

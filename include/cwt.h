@@ -136,6 +136,32 @@ int cwt_plan_describe(cwt_plan_desc *desc, int64_t n, double sfreq, const double
                       int32_t n_freqs, const double *n_cycles, double omega0,
                       const cwt_plan_opts *opts);
 
+/*
+ * Autotuner.  Times the candidate kernel configurations of this plan on the
+ * current device (generic kernel: radix orders 16-first / 8-first /
+ * 4-first, 16 or 24 values per thread, minimal or doubled workgroup; for
+ * power-of-two lengths also the register-resident kernel with table or
+ * power twiddles) on min(C, 16) channels of zeros, keeps the fastest in the
+ * plan, and, when the environment variable CWT_AUTOTUNE_CACHE names a file,
+ * appends the choice there.  cwt_plan_create applies a cached choice for the
+ * same device, padded length, output mode and precision.  A tuned schedule
+ * changes the rounding of the results, not their tolerance.  Synchronises
+ * `stream`; allocates and frees temporary device buffers.  FP32 plans only
+ * (other precisions return CWT_OK unchanged).
+ */
+typedef struct cwt_tune_result {
+    int32_t n_candidates;
+    int32_t kernel;        /* chosen: 0 generic, 1 register-resident            */
+    int32_t variant;       /* register-resident twiddle method (0 table, 1 powers) */
+    int32_t threads;       /* chosen workgroup size                              */
+    int32_t n_passes;
+    int32_t radix[16];
+    float best_ms;         /* best time of one transform of the timed channels   */
+    float default_ms;      /* time of the plan's original configuration          */
+} cwt_tune_result;
+
+int cwt_plan_autotune(cwt_plan *plan, int64_t C, void *stream, cwt_tune_result *result);
+
 /* Lower and upper band-membership of each frequency: band_of_freq[i] is the
  * band index of frequency i, or -1 when it belongs to none (n_freqs ints). */
 int cwt_plan_band_of_freq(const cwt_plan *plan, int32_t *band_of_freq);

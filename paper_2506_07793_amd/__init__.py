@@ -132,6 +132,18 @@ class Plan:
             tw.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream_handle(stream)))
         return H[: int(self.desc.spectrum_bins)], band, tw.view(np.complex64)
 
+    def autotune(self, C, stream=None):
+        """Time the candidate kernel configurations and keep the fastest (cwt_plan_autotune)."""
+        r = _lib.TuneResult()
+        _lib.check(self._lib.cwt_plan_autotune(self._ptr, int(C), _stream_handle(stream),
+                                               ctypes.byref(r)))
+        desc = _lib.PlanDesc()
+        _lib.check(self._lib.cwt_plan_info(self._ptr, ctypes.byref(desc)))
+        self.desc = desc
+        return {"n_candidates": r.n_candidates, "kernel": r.kernel, "variant": r.variant,
+                "threads": r.threads, "radix": [r.radix[i] for i in range(r.n_passes)],
+                "best_ms": r.best_ms, "default_ms": r.default_ms}
+
     # -- execution -------------------------------------------------------
     def output_shape(self, C):
         return (int(C), self.out_rows, self.n)

@@ -89,6 +89,19 @@ class BatchItem(ctypes.Structure):
     ]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [
+        ("n_candidates", ctypes.c_int32),
+        ("kernel", ctypes.c_int32),
+        ("variant", ctypes.c_int32),
+        ("threads", ctypes.c_int32),
+        ("n_passes", ctypes.c_int32),
+        ("radix", ctypes.c_int32 * 16),
+        ("best_ms", ctypes.c_float),
+        ("default_ms", ctypes.c_float),
+    ]
+
+
 class CwtError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("%s (%d): %s" % (ERROR_NAMES.get(code, "CWT_E?"), code, msg))
@@ -117,6 +130,7 @@ SIGNATURES = {
                                             ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_float), _VP]),
     "cwt_plan_destroy": (ctypes.c_int, [_VP, _VP]),
+    "cwt_plan_autotune": (ctypes.c_int, [_VP, _I64, _VP, ctypes.POINTER(TuneResult)]),
     "cwt_batch_workspace_size": (_SZ, [ctypes.POINTER(BatchItem), _I32]),
     "cwt_execute_batch": (ctypes.c_int, [ctypes.POINTER(BatchItem), _I32, _VP, _SZ, _VP]),
     "cwt_server_opts_init": (ctypes.c_int, [ctypes.POINTER(ServerOpts)]),

@@ -112,6 +112,32 @@ static bool try_radix_plan(int L, const int *order, int n_order, int maxv, Radix
     return false;
 }
 
+void radix_candidates(int L, std::vector<RadixPlan> &out)
+{
+    static const int o1[] = {16, 8, 4, 2, 7, 5, 3};
+    static const int o2[] = {8, 4, 2, 7, 5, 3};
+    static const int o3[] = {4, 2, 7, 5, 3};
+    const int *orders[] = {o1, o2, o3};
+    const int lens[] = {7, 6, 5};
+    out.clear();
+    for (int maxv : {16, 24})
+        for (int o = 0; o < 3; ++o) {
+            RadixPlan rp;
+            if (!try_radix_plan(L, orders[o], lens[o], maxv, rp)) continue;
+            for (int mul = 1; mul <= 2; ++mul) {
+                RadixPlan c = rp;
+                c.threads = rp.threads * mul;
+                if (c.threads > 1024) continue;
+                bool dup = false;
+                for (const RadixPlan &q : out)
+                    if (q.threads == c.threads && q.maxv == c.maxv && q.n_pass == c.n_pass &&
+                        std::equal(q.radix, q.radix + q.n_pass, c.radix))
+                        dup = true;
+                if (!dup) out.push_back(c);
+            }
+        }
+}
+
 bool make_radix_plan(int L, RadixPlan &rp)
 {
     static const int o1[] = {16, 8, 4, 2, 7, 5, 3};
@@ -290,6 +316,7 @@ int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
     P.use_fixed = fixed_main_available(P.L) && !(gen && gen[0] == '1');
     const char *var = std::getenv("CWT_FIXED_VARIANT");
     P.variant = var ? std::atoi(var) : 1;
+    apply_tuning_cache(P);
     return CWT_OK;
 }
 
