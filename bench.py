@@ -26,11 +26,18 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
+def kernel_name(plan):
+    """The transform kernel the plan launches (the one the roofline prices)."""
+    if plan.desc.kernel == 1:
+        return "k_fixed_main (multiply + inverse FFT + store, register-resident, L=%d)" % plan.L
+    return "k_main (multiply + inverse FFT + store, runtime radices, L=%d)" % plan.L
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--out", default="complex64", choices=["complex64", "power"])
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing (profiling runs)")
@@ -278,24 +285,23 @@ def main():
             step()
         torch.cuda.synchronize()
 
-        # 1) direct launches, with events around the transform kernel of every
-        #    step: its average duration on the stream it runs on
+        # The timed region: K steps, as direct launches or a replayed HIP graph.
+        # Each transform launch of the direct timed region carries a pair of
+        # events bound to its own dispatch (cwt_plan_timing_start; the events
+        # have no system-scope fence, so they add no cache write-back), which
+        # gives the kernel's average launch duration on the stream it runs on
+        # from the very launches being timed.  A graph cannot carry them:
+        # with --graph the kernel is timed on K direct steps first.
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
-        mids = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                for _ in range(K)]
-        ev0.record(stream)
-        for i in range(K):
-            plan.forward_spectra(x, ws, stream=stream)
-            mids[i][0].record(stream)
-            plan.transform_spectra(C, out, ws, stream=stream)
-            mids[i][1].record(stream)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ms_main = sum(a.elapsed_time(b) for a, b in mids) / K
-
-        # 2) the timed region: K steps, as a replayed HIP graph or direct launches
+        run = step
+        kernel_ms = None
         if args.graph:
+            plan.timing_start(K)
+            for _ in range(K):
+                step()
+            torch.cuda.synchronize()
+            kernel_ms = plan.timing_stop()
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g, stream=stream):
                 step()
@@ -303,7 +309,7 @@ def main():
                 g.replay()
             run = g.replay
         else:
-            run = step
+            plan.timing_start(K)
         torch.cuda.synchronize()
         ev0.record(stream)
         for _ in range(K):
@@ -311,6 +317,10 @@ def main():
         ev1.record(stream)
         torch.cuda.synchronize()
         ms_step = ev0.elapsed_time(ev1) / K
+        if kernel_ms is None:
+            kernel_ms = plan.timing_stop()
+        assert len(kernel_ms) == K, "timed %d of %d transform launches" % (len(kernel_ms), K)
+        ms_main = float(np.mean(kernel_ms))
 
         # Store ceiling: a plain device fill of the same output buffer.
         fill = out.view(torch.float32)
@@ -355,7 +365,7 @@ def main():
                    "channels": C, "samples": N, "freqs": F, "padded_len": plan.L,
                    "radices": plan.radices, "out": args.out,
                    "launch": "hip graph replay" if args.graph else "direct"},
-        "roofline": {"bound": "hbm", "kernel": "k_main (multiply + inverse FFT + store)",
+        "roofline": {"bound": "hbm", "kernel": kernel_name(plan),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes": main_bytes, "avg_ms": ms_main},
@@ -377,12 +387,10 @@ def main():
             for _ in range(3):
                 pp.transform_spectra(C, out, ws, stream=stream)
             torch.cuda.synchronize()
-            ev0.record(stream)
+            pp.timing_start(K)
             for _ in range(K):
                 pp.transform_spectra(C, out, ws, stream=stream)
-            ev1.record(stream)
-            torch.cuda.synchronize()
-        ms_p = ev0.elapsed_time(ev1) / K
+            ms_p = float(np.mean(pp.timing_stop()))
         prec_runs.append({"precision": prec, "transform_ms": ms_p,
                           "transform_pts_per_s": pts / (ms_p * 1e-3),
                           "hbm_frac": main_bytes / (ms_p * 1e-3) / 1e9 / HBM_PEAK_GBS})

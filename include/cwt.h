@@ -207,6 +207,26 @@ int cwt_transform_spectra(const cwt_plan *plan, int64_t C, void *out, void *ws,
 int cwt_plan_copy_tables(const cwt_plan *plan, float *H_host, int32_t *band_host,
                          float *tw_host, void *stream);
 
+/*
+ * Per-launch timing of the transform kernel (the spectral multiply + inverse
+ * FFT + store kernel), for measurements like those of section "Comparison
+ * between devices and software" taken kernel by kernel.
+ * cwt_plan_timing_start creates max_launches pairs of events (host call; not
+ * while a stream is being captured into a graph) and binds one pair to each
+ * of this plan's next max_launches transform dispatches (by cwt_execute or
+ * cwt_transform_spectra, on any stream); each pair takes the start and end
+ * timestamps of that dispatch (hipExtLaunchKernel; the events carry no
+ * system-scope fence, so they add no cache write-back to the stream).
+ * Later dispatches run untimed.  A second start discards earlier records.  cwt_plan_timing_stop waits for the timed
+ * dispatches, writes min(recorded, max) durations in milliseconds, in launch
+ * order, to ms_host (may be NULL when max == 0), the number recorded to
+ * *n_out, and turns timing off.  Not thread-safe against concurrent enqueues
+ * of the same plan.  Errors: CWT_E_INVALID for a NULL plan, max_launches
+ * outside [0, 65536] or max < 0; CWT_E_HIP when an event call fails.
+ */
+int cwt_plan_timing_start(cwt_plan *plan, int32_t max_launches);
+int cwt_plan_timing_stop(cwt_plan *plan, float *ms_host, int32_t max, int32_t *n_out);
+
 /* ---- batches ---------------------------------------------------------- */
 /*
  * Many recordings at once, each with its own plan (length, sampling rate,

@@ -132,6 +132,23 @@ class Plan:
             tw.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream_handle(stream)))
         return H[: int(self.desc.spectrum_bins)], band, tw.view(np.complex64)
 
+    def timing_start(self, max_launches):
+        """Bind dispatch-timed event pairs to the next max_launches transform
+        launches of this plan (cwt_plan_timing_start)."""
+        _lib.check(self._lib.cwt_plan_timing_start(self._ptr, int(max_launches)))
+        self._timing_cap = int(max_launches)
+
+    def timing_stop(self):
+        """Wait for the timed launches; their kernel durations in ms, in launch
+        order (cwt_plan_timing_stop)."""
+        cap = max(getattr(self, "_timing_cap", 0), 0)
+        ms = np.zeros(max(cap, 1), dtype=np.float32)
+        n = ctypes.c_int32(0)
+        _lib.check(self._lib.cwt_plan_timing_stop(
+            self._ptr, ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), cap, ctypes.byref(n)))
+        self._timing_cap = 0
+        return ms[: min(n.value, cap)].astype(np.float64)
+
     def autotune(self, C, stream=None):
         """Time the candidate kernel configurations and keep the fastest (cwt_plan_autotune)."""
         r = _lib.TuneResult()
@@ -147,6 +164,10 @@ class Plan:
     # -- execution -------------------------------------------------------
     def output_shape(self, C):
         return (int(C), self.out_rows, self.n)
+
+    def output_bytes(self, C):
+        elem = 8 if self.out_mode == "complex64" else 4
+        return int(C) * self.out_rows * self.n * elem
 
     def alloc_output(self, C, device="cuda"):
         import torch

@@ -131,6 +131,9 @@ SIGNATURES = {
                                             ctypes.POINTER(ctypes.c_float), _VP]),
     "cwt_plan_destroy": (ctypes.c_int, [_VP, _VP]),
     "cwt_plan_autotune": (ctypes.c_int, [_VP, _I64, _VP, ctypes.POINTER(TuneResult)]),
+    "cwt_plan_timing_start": (ctypes.c_int, [_VP, _I32]),
+    "cwt_plan_timing_stop": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float), _I32,
+                                            ctypes.POINTER(_I32)]),
     "cwt_batch_workspace_size": (_SZ, [ctypes.POINTER(BatchItem), _I32]),
     "cwt_execute_batch": (ctypes.c_int, [ctypes.POINTER(BatchItem), _I32, _VP, _SZ, _VP]),
     "cwt_server_opts_init": (ctypes.c_int, [ctypes.POINTER(ServerOpts)]),

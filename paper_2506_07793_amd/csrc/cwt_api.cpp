@@ -421,6 +421,17 @@ int enqueue_forward(const cwt_plan &P, const float *x, int64_t C, int64_t x_stri
     return CWT_OK;
 }
 
+LaunchEvents next_launch_events(const cwt_plan &P)
+{
+    LaunchEvents ev;
+    if (P.timing_used < P.timing_cap) {
+        ev.start = P.timing_ev[2 * P.timing_used];
+        ev.stop = P.timing_ev[2 * P.timing_used + 1];
+        ++P.timing_used;
+    }
+    return ev;
+}
+
 int enqueue_transform(const cwt_plan &P, int64_t C, void *out, void *ws, hipStream_t s)
 {
     if (C == 0) return CWT_OK;
@@ -440,7 +451,8 @@ int enqueue_transform(const cwt_plan &P, int64_t C, void *out, void *ws, hipStre
     mp.grp_off = P.d_grp_off;
     mp.rp = P.rp;
     mp.variant = P.variant;
-    hipError_t e = (P.use_fixed) ? launch_main_fixed(mp, s) : launch_main(mp, s);
+    const LaunchEvents ev = next_launch_events(P);
+    hipError_t e = (P.use_fixed) ? launch_main_fixed(mp, s, ev) : launch_main(mp, s, ev);
     if (e != hipSuccess) return hip_fail(e, "transform launch");
     return CWT_OK;
 }
@@ -613,12 +625,59 @@ extern "C" int cwt_plan_copy_tables(const cwt_plan *P, float *H_host, int32_t *b
     return CWT_OK;
 }
 
+extern "C" int cwt_plan_timing_start(cwt_plan *P, int32_t max_launches)
+{
+    clear_error();
+    if (!P) return fail(CWT_E_INVALID, "cwt_plan_timing_start: plan is NULL");
+    if (max_launches < 0 || max_launches > 65536)
+        return fail(CWT_E_INVALID, "cwt_plan_timing_start: max_launches %d outside [0, 65536]",
+                    (int)max_launches);
+    P->timing_cap = 0;
+    P->timing_used = 0;
+    hipError_t e = hipSetDevice(P->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice in cwt_plan_timing_start");
+    while ((int)P->timing_ev.size() < 2 * max_launches) {
+        // Timing-only events: no system-scope fence when they complete, so
+        // recording them adds no cache write-back to the timed stream.
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableSystemFence);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate in cwt_plan_timing_start");
+        P->timing_ev.push_back(ev);
+    }
+    P->timing_cap = max_launches;
+    return CWT_OK;
+}
+
+extern "C" int cwt_plan_timing_stop(cwt_plan *P, float *ms_host, int32_t max, int32_t *n_out)
+{
+    clear_error();
+    if (!P) return fail(CWT_E_INVALID, "cwt_plan_timing_stop: plan is NULL");
+    if (max < 0 || (max > 0 && !ms_host))
+        return fail(CWT_E_INVALID, "cwt_plan_timing_stop: max %d with ms_host %p", (int)max,
+                    (void *)ms_host);
+    const int used = P->timing_used;
+    P->timing_cap = 0;
+    P->timing_used = 0;
+    if (n_out) *n_out = used;
+    for (int i = 0; i < used; ++i) {
+        hipError_t e = hipEventSynchronize(P->timing_ev[2 * i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize in cwt_plan_timing_stop");
+        if (i >= max) continue;
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, P->timing_ev[2 * i], P->timing_ev[2 * i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime in cwt_plan_timing_stop");
+        ms_host[i] = ms;
+    }
+    return CWT_OK;
+}
+
 extern "C" int cwt_plan_destroy(cwt_plan *P, void *stream)
 {
     if (!P) return CWT_OK;
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
     release_split_precision(*P);
     free_plan_device(*P);
+    for (hipEvent_t ev : P->timing_ev) (void)hipEventDestroy(ev);
     delete P;
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize in cwt_plan_destroy");
     return CWT_OK;

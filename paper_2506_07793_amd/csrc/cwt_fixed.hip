@@ -10,14 +10,14 @@
 // pass is fully unrolled with constant strides.
 //
 // Inverse kernel (k_fixed_main): the wavelet spectrum of one frequency is
-// non-zero only on a band of K consecutive bins (cyclically).  The workgroup
-// first forms the K products X~[b] H[b] once, into LDS.  When K <= L/16 each
-// radix-16 butterfly of the first Stockham pass sees at most one non-zero
-// input, so that pass reduces to a gather: the second pass's inputs are the
-// band products times exp(2 pi i jm (b - q) / L) (jm, q from the butterfly
-// index).  Wider bands run the full set of passes.  The last pass stores
-// natural-order rows straight from registers (thread t writes samples
-// t + T m).
+// non-zero only on a band of K consecutive bins (cyclically).  Bands of at
+// most 256 bins take the band path below: the bins, pre-multiplied by the
+// phase of each output residue, fill the L LDS slots, and two radix-16
+// passes finish the transform (about two thirds of the full transform's
+// work, and no carrier multiply).  Wider bands stage their K products
+// X~[b] H[b] in LDS and run the full set of passes.  Both leave thread t
+// with the natural-order samples t + T m, which it stores straight to
+// global memory.
 #include "cwt_kernels.hpp"
 #include "fft_core.hpp"
 
@@ -133,12 +133,120 @@ __device__ __forceinline__ void run_passes(cf *v, int t, const cf *__restrict__ 
     }
 }
 
-template <class RL>
-struct Tail;
-template <int R0, int... Rest>
-struct Tail<RList<R0, Rest...>> {
-    using type = RList<Rest...>;
-};
+// ---------------------------------------------------------- band path --
+// Inverse transform of a spectrum that is non-zero on at most 256 consecutive
+// bins (cyclically), for L = 256 NV.  With n = NV u + v (v < NV, u < 256) and
+// every in-band bin written b = s + 256 a (s = b mod 256),
+//   y[NV u + v] = sum_s P_v[s] exp(2 pi i s u / 256),
+//   P_v[s]      = Z[b] exp(2 pi i b v / L),
+// because exp(2 pi i b n / L) = exp(2 pi i s u / 256) exp(2 pi i b v / L)
+// (the factor exp(2 pi i a u) is 1).  So the band's own position (its
+// carrier) is absorbed exactly: NV transforms of length 256, each one radix-16
+// pass without twiddles (over s = k1 + 16 k2, k2 first) and one with the
+// twiddle exp(2 pi i k1 u1 / 256), u = u1 + 16 u2.  The last pass leaves
+// thread t = NV u1 + v with samples t + T u2, the same natural order as the
+// full transform.
+constexpr int kBandMax = 256;
+
+// LDS slot of P_v[s]: rows of 256, bit 4 flipped on odd rows so that the two
+// rows a 32-lane group reads fall in different bank halves.
+__device__ __forceinline__ int band_p_slot(int v, int s) { return v * 256 + (s ^ ((v & 1) << 4)); }
+
+template <int L, int TWM>
+__device__ __forceinline__ void band_transform(const cf *__restrict__ X,
+                                               const float *__restrict__ Hf, int lo_u, int K,
+                                               const cf *__restrict__ tw, cf *lds, int t, cf *v_out)
+{
+    constexpr int NV = L / 256;
+    constexpr int T = L / kV;
+    constexpr int VB = NV < 16 ? NV : 16;  // residues per prologue item
+    constexpr int NIT = 256 * (NV / VB);    // prologue items (bin, residue block)
+    constexpr int LOG_VB = __builtin_ctz(VB);
+    static_assert(NV >= 4 && NV <= 32, "band path covers L = 1024 .. 8192");
+    static_assert(NIT % T == 0, "whole prologue rounds");
+
+    // 1) P_v[s] for every slot: item k < 256 of residue block vb takes bin
+    //    b = lo + k; items k >= K are the empty slots and write zeros.
+#pragma unroll
+    for (int it0 = 0; it0 < NIT; it0 += T) {
+        const int it = it0 + t;
+        const int k = it & 255, vb = it >> 8;
+        const int b = (lo_u + k) & (L - 1);
+        const int s = b & 255;
+        cf zz[VB];
+#pragma unroll
+        for (int i = 0; i < VB; ++i) zz[i] = mk(0.f, 0.f);
+        if (k < K) {
+            const bool upper = b > L / 2;
+            cf xv = X[upper ? L - b : b];
+            if (upper) xv.y = -xv.y;
+            cf z = scale(xv, Hf[k]);
+            // exp(2 pi i b 2^j / L) straight from the table (each rounded once)
+            cf pw[LOG_VB + 1];
+#pragma unroll
+            for (int j = 0; j <= LOG_VB; ++j) pw[j] = tw[(b << j) & (L - 1)];
+            if (NV > VB && vb) z = mul(z, pw[LOG_VB]);  // residues 16 .. 31
+            zz[0] = z;
+#pragma unroll
+            for (int j = 0; j < LOG_VB; ++j)
+#pragma unroll
+                for (int i = 0; i < (1 << j); ++i) zz[(1 << j) + i] = mul(zz[i], pw[j]);
+        }
+#pragma unroll
+        for (int i = 0; i < VB; ++i) lds[band_p_slot(vb * VB + i, s)] = zz[i];
+    }
+    __syncthreads();
+
+    // 2) radix 16 over k2 for thread (k1, v) = (t mod 16, t / 16); slot
+    //    k1 + 16 k2 of row v is base + 16 (k2 xor odd).
+    cf e[16];
+    {
+        const int k1 = t & 15, v = t >> 4;
+        const int odd = v & 1;
+        const cf *pe = lds + v * 256 + k1 + 16 * odd;
+        const cf *po = lds + v * 256 + k1 - 16 * odd;
+#pragma unroll
+        for (int k2 = 0; k2 < 16; ++k2) e[k2] = (k2 & 1) ? po[16 * k2] : pe[16 * k2];
+        Dft<16, 1>::run(e);
+        __syncthreads();  // every thread has read P
+        // element (v, u1, k1) of the exchange goes to
+        //   v 256 + 16 (u1 ^ g) + ((k1 ^ f)),  f = tB mod 16, g = bit 4 of tB,
+        // tB = NV u1 + v the reading thread (g unused when NV = 16), which keeps
+        // both the writes (16 lanes of one v) and the reads (32 lanes of
+        // consecutive tB) on distinct banks.
+        const int xl = k1 ^ (v & 15);
+        const int gofs = (NV == 32) ? ((v >> 4) & 1) << 4 : 0;
+#pragma unroll
+        for (int u1 = 0; u1 < 16; ++u1) {
+            const int c = (NV * u1) & 15;
+            const int g16 = (NV < 16) ? (((NV * u1) >> 4) & 1) << 4 : 0;
+            lds[v * 256 + (((16 * u1) ^ g16) ^ gofs) + (xl ^ c)] = e[u1];
+        }
+    }
+    __syncthreads();
+
+    // 3) twiddle exp(2 pi i k1 u1 / 256) and radix 16 over k1 for thread
+    //    t = NV u1 + v; output u2 is sample t + T u2.
+    {
+        const int u1 = t / NV, v = t & (NV - 1);
+        const int f = t & 15;
+        const int g16 = (NV == 16) ? 0 : ((t >> 4) & 1) << 4;
+        const int row = v * 256 + ((16 * u1) ^ g16);
+        const int rf = row | f;
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) e[k1] = lds[rf ^ k1];
+        cf w[16];
+        if (TWM == kTwTable)
+            table_twiddles<16, 1>(tw, u1 * NV, w);
+        else
+            twiddle_powers<16>(tw[u1 * NV], w);
+#pragma unroll
+        for (int k1 = 1; k1 < 16; ++k1) e[k1] = mul(e[k1], w[k1]);
+        Dft<16, 1>::run(e);
+#pragma unroll
+        for (int u2 = 0; u2 < 16; ++u2) v_out[u2] = e[u2];
+    }
+}
 
 }  // namespace
 
@@ -153,9 +261,7 @@ __global__ void __launch_bounds__(RList<Rs...>::product / kV)
     using RL = RList<Rs...>;
     constexpr int L = RL::product;
     constexpr int T = L / kV;
-    constexpr int R0 = RL::first;
-    constexpr int S0 = L / R0;
-    static_assert(R0 == kV, "the first pass must be radix 16");
+    static_assert(RL::first == kV, "the first pass must be radix 16");
     extern __shared__ cf lds[];
     const int t = threadIdx.x;
     const int N = p.N;
@@ -182,94 +288,28 @@ __global__ void __launch_bounds__(RList<Rs...>::product / kV)
         const int K = bd.K;
         const int lo_u = bd.lo < 0 ? bd.lo + L : bd.lo;
         if (q != qb) __syncthreads();  // previous transform finished with lds
-        // Band products y[k] = X~[b] H[k], b = lo + k (mod L), into lds[0, K).
-        // Loads are issued unconditionally (clamped index) so that they do not
-        // serialise behind branches.
-        {
-            const int nit = (K + T - 1) / T;
-#pragma unroll 2
-            for (int i = 0; i < nit; ++i) {
-                const int k = t + i * T;
-                const int kc = k < K ? k : K - 1;
-                const int b = (lo_u + kc) & (L - 1);
-                const bool upper = b > L / 2;
-                cf xv = X[upper ? L - b : b];
-                const float h = Hf[kc];
-                if (upper) xv.y = -xv.y;
-                if (k < K) lds[k] = scale(xv, h);
-            }
-            if (K <= S0) {
-                // roots of unity of order R0 R1 for the pruned gather below
-                constexpr int NR = R0 * Tail<RL>::type::first;
-                for (int m = t; m < NR; m += T) lds[S0 + m] = tw[m * (L / NR)];
-            }
-        }
-        __syncthreads();
         cf v[kV];
-        if (K <= S0) {
-            // Pruned: gather the second pass's inputs directly.  Pass-1
-            // butterfly j = R0 q + jm reads the in-band bins b = q + G r
-            // (mod S0) times exp(2 pi i jm (b - q) / L); since b - q is a
-            // multiple of G these are roots of unity of order R0 R1, staged
-            // in lds[S0, S0 + R0 R1) next to the band products.
-            constexpr int R1 = Tail<RL>::type::first;
-            constexpr int S1 = L / R1;
-            constexpr int NB = kV / R1;
-            constexpr int G = S1 / R0;       // bin stride between the r inputs
-            constexpr int NQ = S1 / R0;      // butterflies per jm
-            constexpr int NR = R0 * R1;      // root order
-            constexpr int LOG_S0 = __builtin_ctz(S0);
-            static_assert(Tail<typename Tail<RL>::type>::type::count > 0,
-                          "at least three passes");
-#pragma unroll
-            for (int kb = 0; kb < NB; ++kb) {
-                // consecutive lanes take consecutive q (same jm), which keeps
-                // the root reads to a few distinct LDS addresses per wave
-                const int jj = t + kb * T;
-                const int qq = jj & (NQ - 1);
-                const int jm = jj / NQ;
-                const int c0 = (qq - lo_u) & (S0 - 1);
-                const int A = (lo_u - qq + c0) >> LOG_S0;  // exact multiple of S0
-                const int acc = jm * R1 * A;
-#pragma unroll
-                for (int r = 0; r < R1; ++r) {
-                    const int u = c0 + G * r;
-                    const int o = u & (S0 - 1);
-                    const int ri = (acc + jm * r - ((u >= S0) ? jm * R1 : 0)) & (NR - 1);
-                    cf yw = mk(0.f, 0.f);
-                    // whole 16-lane groups share o, so this branch is mostly
-                    // uniform per wave and skips the out-of-band rows
-                    if (o < K) yw = mul(lds[o], lds[S0 + ri]);
-                    v[kb + r * NB] = yw;
-                }
-            }
-            // second pass without its twiddle (folded into the gather)
-#pragma unroll
-            for (int kb = 0; kb < NB; ++kb) {
-                cf e[R1];
-#pragma unroll
-                for (int r = 0; r < R1; ++r) e[r] = v[kb + r * NB];
-                Dft<R1, 1>::run(e);
-#pragma unroll
-                for (int r = 0; r < R1; ++r) v[kb + r * NB] = e[r];
-            }
-            using After = typename Tail<typename Tail<RL>::type>::type;
-            if constexpr (After::count > 0) {
-                __syncthreads();  // every thread has read the band products and roots
-#pragma unroll
-                for (int kb = 0; kb < NB; ++kb) {
-                    const int jj = t + kb * T;
-                    const int qq = jj & (NQ - 1);
-                    const int jm = jj / NQ;
-                    const int base = NR * qq + jm;  // (j - jm) R1 + jm, j = R0 qq + jm
-#pragma unroll
-                    for (int r = 0; r < R1; ++r) lds[sw(base + r * R0)] = v[kb + r * NB];
-                }
-                __syncthreads();
-                load_lds_columns<L>(v, t, lds);
-                run_passes<1, L, R0 * R1, TWM>(v, t, tw, lds, After{});
-            }
+        if (K <= kBandMax) {
+            band_transform<L, TWM>(X, Hf, lo_u, K, tw, lds, t, v);
         } else {
+            // Band products y[k] = X~[b] H[k], b = lo + k (mod L), into lds[0, K).
+            // Loads are issued unconditionally (clamped index) so that they do not
+            // serialise behind branches.
+            {
+                const int nit = (K + T - 1) / T;
+#pragma unroll 2
+                for (int i = 0; i < nit; ++i) {
+                    const int k = t + i * T;
+                    const int kc = k < K ? k : K - 1;
+                    const int b = (lo_u + kc) & (L - 1);
+                    const bool upper = b > L / 2;
+                    cf xv = X[upper ? L - b : b];
+                    const float h = Hf[kc];
+                    if (upper) xv.y = -xv.y;
+                    if (k < K) lds[k] = scale(xv, h);
+                }
+            }
+            __syncthreads();
 #pragma unroll
             for (int m = 0; m < kV; ++m) {
                 const int o = (t + T * m - lo_u) & (L - 1);
@@ -375,7 +415,7 @@ hipError_t launch_forward_fixed(const FwdParams &p, hipStream_t s)
 }
 
 template <int MODE, int TWM, int... Rs>
-static hipError_t launch_fixed_t(const MainParams &p, hipStream_t s)
+static hipError_t launch_fixed_t(const MainParams &p, hipStream_t s, LaunchEvents ev)
 {
     constexpr int L = RList<Rs...>::product;
     const size_t lds = (size_t)L * sizeof(cf);
@@ -385,26 +425,26 @@ static hipError_t launch_fixed_t(const MainParams &p, hipStream_t s)
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_fixed_main<MODE, TWM, Rs...>), dim3(p.C * p.n_rows), dim3(L / kV),
-                       lds, s, p);
+    hipExtLaunchKernelGGL((k_fixed_main<MODE, TWM, Rs...>), dim3(p.C * p.n_rows), dim3(L / kV),
+                          lds, s, ev.start, ev.stop, 0, p);
     return hipGetLastError();
 }
 
 template <int TWM, int... Rs>
-static hipError_t launch_fixed_modes_t(const MainParams &p, hipStream_t s)
+static hipError_t launch_fixed_modes_t(const MainParams &p, hipStream_t s, LaunchEvents ev)
 {
     switch (p.out_mode) {
-    case kOutComplex: return launch_fixed_t<kOutComplex, TWM, Rs...>(p, s);
-    case kOutPower: return launch_fixed_t<kOutPower, TWM, Rs...>(p, s);
-    default: return launch_fixed_t<kOutBand, TWM, Rs...>(p, s);
+    case kOutComplex: return launch_fixed_t<kOutComplex, TWM, Rs...>(p, s, ev);
+    case kOutPower: return launch_fixed_t<kOutPower, TWM, Rs...>(p, s, ev);
+    default: return launch_fixed_t<kOutBand, TWM, Rs...>(p, s, ev);
     }
 }
 
 template <int... Rs>
-static hipError_t launch_fixed_modes(const MainParams &p, hipStream_t s)
+static hipError_t launch_fixed_modes(const MainParams &p, hipStream_t s, LaunchEvents ev)
 {
-    return p.variant == 1 ? launch_fixed_modes_t<kTwPowers, Rs...>(p, s)
-                          : launch_fixed_modes_t<kTwTable, Rs...>(p, s);
+    return p.variant == 1 ? launch_fixed_modes_t<kTwPowers, Rs...>(p, s, ev)
+                          : launch_fixed_modes_t<kTwTable, Rs...>(p, s, ev);
 }
 
 bool fixed_main_available(int L)
@@ -412,13 +452,13 @@ bool fixed_main_available(int L)
     return L == 1024 || L == 2048 || L == 4096 || L == 8192;
 }
 
-hipError_t launch_main_fixed(const MainParams &p, hipStream_t s)
+hipError_t launch_main_fixed(const MainParams &p, hipStream_t s, LaunchEvents ev)
 {
     switch (p.rp.L) {
-    case 1024: return launch_fixed_modes<16, 16, 4>(p, s);
-    case 2048: return launch_fixed_modes<16, 16, 8>(p, s);
-    case 4096: return launch_fixed_modes<16, 16, 16>(p, s);
-    case 8192: return launch_fixed_modes<16, 16, 16, 2>(p, s);
+    case 1024: return launch_fixed_modes<16, 16, 4>(p, s, ev);
+    case 2048: return launch_fixed_modes<16, 16, 8>(p, s, ev);
+    case 4096: return launch_fixed_modes<16, 16, 16>(p, s, ev);
+    case 8192: return launch_fixed_modes<16, 16, 16, 2>(p, s, ev);
     default: return hipErrorNotSupported;
     }
 }

@@ -36,6 +36,11 @@ struct cwt_plan {
     int *d_grp_freq = nullptr;
     int *d_grp_off = nullptr;
     cwt_split_state *split = nullptr;
+    // Per-launch timing of the transform kernel (cwt_plan_timing_start/stop):
+    // event pairs bound to the next `timing_cap` transform dispatches.
+    std::vector<hipEvent_t> timing_ev;  // 2 per slot: start, stop
+    int timing_cap = 0;
+    mutable int timing_used = 0;
 };
 
 namespace cwtrt {
@@ -59,6 +64,8 @@ size_t workspace_bytes(const cwt_plan &P, int64_t C);
 int enqueue_forward(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride, void *ws,
                     hipStream_t s);
 int enqueue_transform(const cwt_plan &P, int64_t C, void *out, void *ws, hipStream_t s);
+// Events for the next transform dispatch while timing is on, else a null pair.
+cwtk::LaunchEvents next_launch_events(const cwt_plan &P);
 int enqueue_execute(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride, void *out,
                     void *ws, hipStream_t s);
 
@@ -66,6 +73,7 @@ int enqueue_execute(const cwt_plan &P, const float *x, int64_t C, int64_t x_stri
 bool split_precision_available();
 int prepare_split_precision(cwt_plan &P, hipStream_t s);
 void release_split_precision(cwt_plan &P);
+
 size_t split_workspace_bytes(const cwt_plan &P, int64_t C);
 int enqueue_execute_split(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride,
                           void *out, void *ws, hipStream_t s);

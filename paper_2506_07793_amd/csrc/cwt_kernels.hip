@@ -339,28 +339,29 @@ hipError_t launch_batch_main(const MainParams *items, const BatchTask *tasks, in
 }
 
 template <int MAXV, int MODE>
-static hipError_t launch_main_t(const MainParams &p, hipStream_t s)
+static hipError_t launch_main_t(const MainParams &p, hipStream_t s, LaunchEvents ev)
 {
     const int blocks = p.C * p.n_rows;
     const size_t lds = (size_t)p.rp.L * sizeof(cf);
     set_lds_limit((const void *)k_main<MAXV, MODE>, lds);
-    hipLaunchKernelGGL((k_main<MAXV, MODE>), dim3(blocks), dim3(p.rp.threads), lds, s, p);
+    hipExtLaunchKernelGGL((k_main<MAXV, MODE>), dim3(blocks), dim3(p.rp.threads), lds, s,
+                          ev.start, ev.stop, 0, p);
     return hipGetLastError();
 }
 
-hipError_t launch_main(const MainParams &p, hipStream_t s)
+hipError_t launch_main(const MainParams &p, hipStream_t s, LaunchEvents ev)
 {
     if (p.rp.maxv <= 16) {
         switch (p.out_mode) {
-        case kOutComplex: return launch_main_t<16, kOutComplex>(p, s);
-        case kOutPower: return launch_main_t<16, kOutPower>(p, s);
-        default: return launch_main_t<16, kOutBand>(p, s);
+        case kOutComplex: return launch_main_t<16, kOutComplex>(p, s, ev);
+        case kOutPower: return launch_main_t<16, kOutPower>(p, s, ev);
+        default: return launch_main_t<16, kOutBand>(p, s, ev);
         }
     }
     switch (p.out_mode) {
-    case kOutComplex: return launch_main_t<24, kOutComplex>(p, s);
-    case kOutPower: return launch_main_t<24, kOutPower>(p, s);
-    default: return launch_main_t<24, kOutBand>(p, s);
+    case kOutComplex: return launch_main_t<24, kOutComplex>(p, s, ev);
+    case kOutPower: return launch_main_t<24, kOutPower>(p, s, ev);
+    default: return launch_main_t<24, kOutBand>(p, s, ev);
     }
 }
 

@@ -1,6 +1,7 @@
 // Kernel launch interface shared by the host runtime of libcwt.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -121,12 +122,19 @@ struct GenParams {
     float2 *tw;            // [L]
 };
 
+// Optional pair of events bound to one kernel dispatch (hipExtLaunchKernel):
+// they take the dispatch's own start and end timestamps.  Null: untimed.
+struct LaunchEvents {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
+
 hipError_t launch_generate(const GenParams &p, int total_bins, hipStream_t s);
 hipError_t launch_forward(const FwdParams &p, hipStream_t s);
-hipError_t launch_main(const MainParams &p, hipStream_t s);
+hipError_t launch_main(const MainParams &p, hipStream_t s, LaunchEvents ev = {});
 // Register-resident kernels for the padded lengths that have one.
 bool fixed_main_available(int L);
-hipError_t launch_main_fixed(const MainParams &p, hipStream_t s);
+hipError_t launch_main_fixed(const MainParams &p, hipStream_t s, LaunchEvents ev = {});
 hipError_t launch_forward_fixed(const FwdParams &p, hipStream_t s);
 
 }  // namespace cwtk

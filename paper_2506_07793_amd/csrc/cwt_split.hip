@@ -236,19 +236,20 @@ void release_split_precision(cwt_plan &) {}
 size_t split_workspace_bytes(const cwt_plan &, int64_t) { return 0; }
 
 template <int MODE, int PREC>
-static hipError_t launch_split_t(const MainParams &mp, hipStream_t s)
+static hipError_t launch_split_t(const MainParams &mp, hipStream_t s, LaunchEvents ev)
 {
-    hipLaunchKernelGGL((k_split_main<MODE, PREC>), dim3(mp.C * mp.n_rows), dim3(kT), 0, s, mp);
+    hipExtLaunchKernelGGL((k_split_main<MODE, PREC>), dim3(mp.C * mp.n_rows), dim3(kT), 0, s,
+                          ev.start, ev.stop, 0, mp);
     return hipGetLastError();
 }
 
 template <int PREC>
-static hipError_t launch_split_modes(const MainParams &mp, hipStream_t s)
+static hipError_t launch_split_modes(const MainParams &mp, hipStream_t s, LaunchEvents ev)
 {
     switch (mp.out_mode) {
-    case kOutComplex: return launch_split_t<kOutComplex, PREC>(mp, s);
-    case kOutPower: return launch_split_t<kOutPower, PREC>(mp, s);
-    default: return launch_split_t<kOutBand, PREC>(mp, s);
+    case kOutComplex: return launch_split_t<kOutComplex, PREC>(mp, s, ev);
+    case kOutPower: return launch_split_t<kOutPower, PREC>(mp, s, ev);
+    default: return launch_split_t<kOutBand, PREC>(mp, s, ev);
     }
 }
 
@@ -270,9 +271,10 @@ int enqueue_transform_split(const cwt_plan &P, int64_t C, void *out, void *ws, h
     mp.grp_freq = P.d_grp_freq;
     mp.grp_off = P.d_grp_off;
     mp.rp = P.rp;
+    const LaunchEvents ev = next_launch_events(P);
     hipError_t e = (P.opts.precision == CWT_PREC_SPLIT_F16)
-                       ? launch_split_modes<CWT_PREC_SPLIT_F16>(mp, s)
-                       : launch_split_modes<CWT_PREC_SPLIT_BF16>(mp, s);
+                       ? launch_split_modes<CWT_PREC_SPLIT_F16>(mp, s, ev)
+                       : launch_split_modes<CWT_PREC_SPLIT_BF16>(mp, s, ev);
     if (e != hipSuccess) return hip_fail(e, "split-precision transform launch");
     return CWT_OK;
 }

@@ -139,6 +139,10 @@ def test_validation_raw_abi():
     assert lib.cwt_execute(None, None, 1, None, None, 0, None) == _lib.CWT_E_INVALID
     assert lib.cwt_plan_destroy(None, None) == _lib.CWT_OK
     assert lib.cwt_workspace_size(None, 4) == 0
+    # per-launch timing: NULL plan rejected
+    n = ctypes.c_int32(-1)
+    assert lib.cwt_plan_timing_start(None, 4) == _lib.CWT_E_INVALID
+    assert lib.cwt_plan_timing_stop(None, None, 0, ctypes.byref(n)) == _lib.CWT_E_INVALID
 
 
 def test_band_membership_rule():

@@ -299,3 +299,81 @@ def test_fixed_and_generic_kernels_agree(out, monkeypatch):
             assert e <= TOL_P
     pg.close()
     pf.close()
+
+
+@pytest.mark.parametrize("generic", [False, True])
+def test_dispatch_timing_records_each_launch(generic, monkeypatch):
+    """cwt_plan_timing_start/stop: one positive duration per timed transform
+    launch (later launches untimed), results unchanged by timing, bad
+    arguments rejected, and a stop without a start records nothing."""
+    x, sfreq, freqs, cyc = _eeg(4)
+    if generic:
+        monkeypatch.setenv("CWT_GENERIC_ONLY", "1")
+    plan = cwt.Plan(4096, sfreq, freqs, n_cycles=cyc)
+    assert plan.desc.kernel == (0 if generic else 1)
+    xt = torch.from_numpy(x).cuda()
+    ref = plan.execute(xt).clone()
+    assert len(plan.timing_stop()) == 0
+    plan.timing_start(3)
+    outs = [plan.execute(xt) for _ in range(5)]
+    ms = plan.timing_stop()
+    assert len(ms) == 3, ms
+    assert np.all(ms > 0) and np.all(ms < 1000), ms
+    for o in outs:
+        assert torch.equal(o, ref)
+    # a second start reuses the events; the stage call is timed as well
+    ws = plan.alloc_workspace(4)
+    out = plan.alloc_output(4)
+    plan.forward_spectra(xt, ws)
+    plan.timing_start(2)
+    plan.transform_spectra(4, out, ws)
+    ms2 = plan.timing_stop()
+    assert len(ms2) == 1 and ms2[0] > 0
+    assert torch.equal(out, ref)
+    from paper_2506_07793_amd import _lib
+    lib = _lib.load()
+    assert lib.cwt_plan_timing_start(plan.handle, -1) == _lib.CWT_E_INVALID
+    assert lib.cwt_plan_timing_start(plan.handle, 70000) == _lib.CWT_E_INVALID
+    assert lib.cwt_plan_timing_stop(plan.handle, None, 2, None) == _lib.CWT_E_INVALID
+    plan.close()
+
+
+@pytest.mark.parametrize("L", [1024, 2048, 4096, 8192])
+@pytest.mark.parametrize("out", ["complex64", "power"])
+def test_band_path_edges(L, out):
+    """Register-resident lengths: rows whose spectrum band has at most 256
+    bins take the band path, wider ones the full passes.  The grid is chosen
+    so that both kinds occur, including bands that wrap past bin 0, bands that
+    end at the last positive bin and bands of 1 to 256 bins; every row is
+    checked against the oracle."""
+    sfreq = 1000.0
+    N = L - 37  # ragged crop
+    # 20 log-spaced frequencies alternating 3 and 12 cycles, one 3-cycle wavelet
+    # at 499 Hz (band = whole spectrum) and a long wavelet at 495 Hz whose
+    # narrow band runs up to the last positive bin
+    freqs = np.concatenate([synth.log_freqs(0.3, 480.0, 20), [499.0, 495.0]])
+    cyc = np.concatenate([np.where(np.arange(20) % 2 == 0, 3.0, 12.0), [3.0, 60.0 * L / 1024]])
+    rng = np.random.default_rng(L)
+    x = rng.normal(0, 20, size=(2, N)).astype(np.float32)
+    plan, W = _run(x, sfreq, freqs, cyc, pad="pow2", out=out)
+    assert plan.L == L and plan.desc.kernel == 1
+    _, band, _ = plan.tables()
+    lo, K = band[:, 0], band[:, 1]
+    assert (K <= 256).any() and (K > 256).any(), K
+    narrow = K <= 256
+    assert (lo[narrow] < 0).any(), "no narrow band wrapping past bin 0"
+    # (the spectrum vanishes at negative frequencies, so a band ends at the
+    # last positive bin at the latest; bands wrapping past bin 0 read the
+    # conjugated upper half)
+    assert ((lo + K == L // 2) & narrow).any(), "no narrow band up to the last positive bin"
+    assert (K == L).any(), "no whole-spectrum band"
+    ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc, L=L)
+    if out == "complex64":
+        _parity(W, ref, "band path L=%d" % L)
+    else:
+        Pr = oracle.power(ref)
+        e = np.max(np.abs(W - Pr)) / Pr.max()
+        print("band path L=%d power e=%.3e" % (L, e))
+        assert e <= TOL_P
+    plan.close()
+
