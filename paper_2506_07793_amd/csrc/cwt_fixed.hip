@@ -322,21 +322,27 @@ __global__ void __launch_bounds__(RList<Rs...>::product / kV)
         float2 *ocx = reinterpret_cast<float2 *>(p.out) + ((int64_t)c * p.n_rows + f) * N;
         float *opw = reinterpret_cast<float *>(p.out) + ((int64_t)c * p.n_rows + f) * N;
         const bool first = (q == qb), final_f = (q == qe - 1);
-#pragma unroll
-        for (int m = 0; m < kV; ++m) {
+        auto store = [&](int m) {
             const int ts = t + T * m;
-            if (ts < N) {
-                const cf w = v[m];
-                const float pw = w.x * w.x + w.y * w.y;
-                if (MODE == kOutComplex) {
-                    __builtin_nontemporal_store(f2v{w.x, w.y}, reinterpret_cast<f2v *>(ocx + ts));
-                } else if (MODE == kOutPower) {
-                    __builtin_nontemporal_store(pw, opw + ts);
-                } else {
-                    float a = first ? pw : orow_band[ts] + pw;
-                    orow_band[ts] = final_f ? a * inv_n : a;
-                }
+            const cf w = v[m];
+            const float pw = w.x * w.x + w.y * w.y;
+            if (MODE == kOutComplex) {
+                *reinterpret_cast<f2v *>(ocx + ts) = f2v{w.x, w.y};
+            } else if (MODE == kOutPower) {
+                opw[ts] = pw;
+            } else {
+                float a = first ? pw : orow_band[ts] + pw;
+                orow_band[ts] = final_f ? a * inv_n : a;
             }
+        };
+        if (N == L) {
+            // whole rows (uniform branch): no per-sample bounds test
+#pragma unroll
+            for (int m = 0; m < kV; ++m) store(m);
+        } else {
+#pragma unroll
+            for (int m = 0; m < kV; ++m)
+                if (t + T * m < N) store(m);
         }
     }
 }
