@@ -44,7 +44,15 @@ struct ClassInfo {
     int threads = 0, maxv = 16;
     int max_L = 1;
     std::vector<BatchTask> fwd, main;
+    std::vector<double> fwd_cost, main_cost;  // sort keys (larger first)
 };
+
+// Estimated cost of one transform row of a plan: L log2 L (FFT work).
+double row_cost(const cwt_plan &P) { return P.L * std::log2((double)std::max(2, P.L)); }
+
+// Rows per transform task: enough consecutive rows of one channel that a
+// task is worth an atomic claim and a barrier, few enough to balance.
+constexpr double kTaskCost = 1 << 20;
 
 struct Layout {
     size_t counters = 0, fwd_items = 0, main_items = 0, fwd_tasks = 0, main_tasks = 0, xh = 0,
@@ -138,25 +146,80 @@ Staging &staging(int dev)
     return *p;
 }
 
+// Side streams and fork/join events of one device: each class runs on its
+// own stream so that the classes overlap (in a captured graph they become
+// parallel branches between the counter reset and the join).
+struct Fork {
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
+};
+
+int get_fork(int dev, size_t n, Fork *&out)
+{
+    static std::mutex m;
+    static std::map<int, Fork *> forks;  // live until process exit
+    std::lock_guard<std::mutex> lk(m);
+    Fork *&f = forks[dev];
+    if (!f) f = new Fork();
+    hipError_t e = hipSuccess;
+    const unsigned flags = hipEventDisableTiming | hipEventDisableSystemFence;
+    if (!f->fork) e = hipEventCreateWithFlags(&f->fork, flags);
+    while (e == hipSuccess && f->side.size() < n) {
+        hipStream_t st = nullptr;
+        hipEvent_t ev = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);  // default priority
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, flags);
+        if (e == hipSuccess) {
+            f->side.push_back(st);
+            f->join.push_back(ev);
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, "batch side streams");
+    out = f;
+    return CWT_OK;
+}
+
 int enqueue_kernels(const std::vector<ClassInfo> &classes, char *ws, const Layout &Lo,
                     hipStream_t s)
 {
     hipError_t e = launch_zero_counters(reinterpret_cast<int *>(ws + Lo.counters),
                                         2 * (int)classes.size(), s);
     if (e != hipSuccess) return hip_fail(e, "counter reset");
+    const bool fork = classes.size() > 1;
+    Fork *fk = nullptr;
+    if (fork) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        int rc = get_fork(dev, classes.size(), fk);
+        if (rc != CWT_OK) return rc;
+        e = hipEventRecord(fk->fork, s);
+        if (e != hipSuccess) return hip_fail(e, "batch fork");
+    }
     size_t f_off = 0, m_off = 0;
     for (size_t k = 0; k < classes.size(); ++k) {
         const ClassInfo &c = classes[k];
+        hipStream_t sk = s;
+        if (fork) {
+            sk = fk->side[k];
+            e = hipStreamWaitEvent(sk, fk->fork, 0);
+            if (e != hipSuccess) return hip_fail(e, "batch fork wait");
+        }
         int *ctr = reinterpret_cast<int *>(ws + Lo.counters) + 2 * k;
-        const size_t lds = (size_t)c.max_L * sizeof(float2);
+        const size_t lds = generic_lds_bytes(c.max_L);
         e = launch_batch_forward(reinterpret_cast<const FwdParams *>(ws + Lo.fwd_items),
                                  reinterpret_cast<const BatchTask *>(ws + Lo.fwd_tasks) + f_off,
-                                 (int)c.fwd.size(), ctr, c.threads, c.maxv, lds, s);
+                                 (int)c.fwd.size(), ctr, c.threads, c.maxv, lds, sk);
         if (e != hipSuccess) return hip_fail(e, "batch forward launch");
         e = launch_batch_main(reinterpret_cast<const MainParams *>(ws + Lo.main_items),
                               reinterpret_cast<const BatchTask *>(ws + Lo.main_tasks) + m_off,
-                              (int)c.main.size(), ctr + 1, c.threads, c.maxv, lds, s);
+                              (int)c.main.size(), ctr + 1, c.threads, c.maxv, lds, sk);
         if (e != hipSuccess) return hip_fail(e, "batch transform launch");
+        if (fork) {
+            e = hipEventRecord(fk->join[k], sk);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, fk->join[k], 0);
+            if (e != hipSuccess) return hip_fail(e, "batch join");
+        }
         f_off += c.fwd.size();
         m_off += c.main.size();
     }
@@ -200,23 +263,43 @@ extern "C" int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *w
         c.maxv = P.rp.maxv;
         c.max_L = std::max(c.max_L, P.L);
         const int rows = (P.opts.out == CWT_OUT_BANDPOWER_F32) ? P.n_bands : P.F;
-        const double lg = std::log2((double)std::max(2, P.L));
-        const int fcost = (int)std::min(2e9, P.L * lg);
-        for (int pr = 0; pr < (int)((items[i].C + 1) / 2); ++pr) c.fwd.push_back({i, pr, 0, fcost});
+        const double rc = row_cost(P);
+        for (int pr = 0; pr < (int)((items[i].C + 1) / 2); ++pr) {
+            c.fwd.push_back({i, pr, 0, 1});
+            c.fwd_cost.push_back(rc);
+        }
+        // band-power rows cost their number of frequencies
+        auto freqs_in = [&](int r) {
+            return (P.opts.out == CWT_OUT_BANDPOWER_F32) ? P.grp_off[r + 1] - P.grp_off[r] : 1;
+        };
         for (int ch = 0; ch < (int)items[i].C; ++ch)
-            for (int r = 0; r < rows; ++r) {
-                int per = 1;
-                if (P.opts.out == CWT_OUT_BANDPOWER_F32) per = P.grp_off[r + 1] - P.grp_off[r];
-                c.main.push_back({i, ch, r, (int)std::min(2e9, per * P.L * lg)});
+            for (int r = 0; r < rows;) {
+                int nr = 0;
+                double cost = 0;
+                while (r + nr < rows && (nr == 0 || cost + freqs_in(r + nr) * rc <= kTaskCost)) {
+                    cost += freqs_in(r + nr) * rc;
+                    ++nr;
+                }
+                c.main.push_back({i, ch, r, nr});
+                c.main_cost.push_back(cost);
+                r += nr;
             }
     }
     std::vector<ClassInfo> classes;
     size_t n_fwd = 0, n_main = 0;
     for (auto &kv : by_class) {
         ClassInfo c = std::move(kv.second);
-        auto by_cost = [](const BatchTask &a, const BatchTask &b) { return a.cost > b.cost; };
-        std::stable_sort(c.fwd.begin(), c.fwd.end(), by_cost);
-        std::stable_sort(c.main.begin(), c.main.end(), by_cost);
+        auto sort_by_cost = [](std::vector<BatchTask> &t, const std::vector<double> &cost) {
+            std::vector<size_t> ix(t.size());
+            for (size_t k = 0; k < ix.size(); ++k) ix[k] = k;
+            std::stable_sort(ix.begin(), ix.end(),
+                             [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+            std::vector<BatchTask> out(t.size());
+            for (size_t k = 0; k < ix.size(); ++k) out[k] = t[ix[k]];
+            t.swap(out);
+        };
+        sort_by_cost(c.fwd, c.fwd_cost);
+        sort_by_cost(c.main, c.main_cost);
         n_fwd += c.fwd.size();
         n_main += c.main.size();
         classes.push_back(std::move(c));

@@ -74,6 +74,9 @@ __device__ __forceinline__ void forward_task(const FwdParams &p, int pair)
 
     auto lds_load = [](int idx) -> cf { return lds[idx]; };
     auto lds_store = [](int, int idx, cf v) { lds[idx] = v; };
+    auto lds_load_sw = [](int idx) -> cf { return lds[first_pass_slot(idx)]; };
+    auto lds_store_sw = [](int, int idx, cf v) { lds[first_pass_slot(idx)] = v; };
+    const bool swz = p.rp.n_pass >= 2 && (p.rp.radix[0] & 1) == 0;
     auto in_load = [=](int idx) -> cf {
         cf z = mk(0.f, 0.f);
         if (idx < N) {
@@ -86,8 +89,12 @@ __device__ __forceinline__ void forward_task(const FwdParams &p, int pair)
     int Ns = 1;
     for (int i = 0; i < p.rp.n_pass; ++i) {
         const int R = p.rp.radix[i];
-        if (i == 0)
+        if (i == 0 && swz)
+            stockham_pass_rt<-1, MAXV, true>(R, L, Ns, T, tid, tw, in_load, lds_store_sw);
+        else if (i == 0)
             stockham_pass_rt<-1, MAXV, true>(R, L, Ns, T, tid, tw, in_load, lds_store);
+        else if (i == 1 && swz)
+            stockham_pass_rt<-1, MAXV, true>(R, L, Ns, T, tid, tw, lds_load_sw, lds_store);
         else
             stockham_pass_rt<-1, MAXV, true>(R, L, Ns, T, tid, tw, lds_load, lds_store);
         __syncthreads();
@@ -121,7 +128,7 @@ static void set_lds_limit(const void *fn, size_t bytes)
 hipError_t launch_forward(const FwdParams &p, hipStream_t s)
 {
     const int blocks = (p.C + 1) / 2;
-    const size_t lds = (size_t)p.rp.L * sizeof(cf);
+    const size_t lds = generic_lds_bytes(p.rp.L);
     if (p.rp.maxv <= 16) {
         set_lds_limit((const void *)k_forward<16>, lds);
         hipLaunchKernelGGL(k_forward<16>, dim3(blocks), dim3(p.rp.threads), lds, s, p);
@@ -159,6 +166,9 @@ __device__ __forceinline__ void main_task(const MainParams &p, int c, int row)
 
     auto lds_load = [](int idx) -> cf { return lds[idx]; };
     auto lds_store = [](int, int idx, cf v) { lds[idx] = v; };
+    auto lds_load_sw = [](int idx) -> cf { return lds[first_pass_slot(idx)]; };
+    auto lds_store_sw = [](int, int idx, cf v) { lds[first_pass_slot(idx)] = v; };
+    const bool swz = n_pass >= 2 && (p.rp.radix[0] & 1) == 0;
 
     for (int q = qb; q < qe; ++q) {
         const int f = (MODE == kOutBand) ? p.grp_freq[q] : q;
@@ -208,14 +218,20 @@ __device__ __forceinline__ void main_task(const MainParams &p, int c, int row)
             const int R = p.rp.radix[i];
             const bool last = (i == n_pass - 1);
             if (!last) {
-                if (i == 0)
+                if (i == 0 && swz)
+                    stockham_pass_rt<1, MAXV, true>(R, L, Ns, T, tid, tw, spec_load, lds_store_sw);
+                else if (i == 0)
                     stockham_pass_rt<1, MAXV, true>(R, L, Ns, T, tid, tw, spec_load, lds_store);
+                else if (i == 1 && swz)
+                    stockham_pass_rt<1, MAXV, true>(R, L, Ns, T, tid, tw, lds_load_sw, lds_store);
                 else
                     stockham_pass_rt<1, MAXV, true>(R, L, Ns, T, tid, tw, lds_load, lds_store);
                 __syncthreads();
             } else {
                 if (i == 0)
                     stockham_pass_rt<1, MAXV, false>(R, L, Ns, T, tid, tw, spec_load, epi);
+                else if (i == 1 && swz)
+                    stockham_pass_rt<1, MAXV, true>(R, L, Ns, T, tid, tw, lds_load_sw, epi);
                 else
                     stockham_pass_rt<1, MAXV, true>(R, L, Ns, T, tid, tw, lds_load, epi);
             }
@@ -269,12 +285,14 @@ __global__ void __launch_bounds__(1024)
         if (t >= n) break;
         const BatchTask tk = tasks[t];
         const MainParams &p = items[tk.item];
-        switch (p.out_mode) {
-        case kOutComplex: main_task<MAXV, kOutComplex>(p, tk.a, tk.b); break;
-        case kOutPower: main_task<MAXV, kOutPower>(p, tk.a, tk.b); break;
-        default: main_task<MAXV, kOutBand>(p, tk.a, tk.b); break;
+        for (int r = tk.b; r < tk.b + tk.n; ++r) {
+            switch (p.out_mode) {
+            case kOutComplex: main_task<MAXV, kOutComplex>(p, tk.a, r); break;
+            case kOutPower: main_task<MAXV, kOutPower>(p, tk.a, r); break;
+            default: main_task<MAXV, kOutBand>(p, tk.a, r); break;
+            }
+            __syncthreads();  // the next row reuses LDS
         }
-        __syncthreads();
     }
 }
 
@@ -342,7 +360,7 @@ template <int MAXV, int MODE>
 static hipError_t launch_main_t(const MainParams &p, hipStream_t s, LaunchEvents ev)
 {
     const int blocks = p.C * p.n_rows;
-    const size_t lds = (size_t)p.rp.L * sizeof(cf);
+    const size_t lds = generic_lds_bytes(p.rp.L);
     set_lds_limit((const void *)k_main<MAXV, MODE>, lds);
     hipExtLaunchKernelGGL((k_main<MAXV, MODE>), dim3(blocks), dim3(p.rp.threads), lds, s,
                           ev.start, ev.stop, 0, p);

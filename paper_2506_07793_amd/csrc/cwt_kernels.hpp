@@ -59,12 +59,12 @@ struct MainParams {
 
 // ------------------------------------------------------------- batched --
 // One task of a persistent batch kernel: item index and its channel pair
-// (forward) or (channel, output row) (transform).
+// (forward) or a run of consecutive output rows of one channel (transform).
 struct BatchTask {
     int item;
-    int a;
-    int b;
-    int cost;  // sort key (larger first)
+    int a;  // channel pair (forward) or channel (transform)
+    int b;  // first output row (transform)
+    int n;  // number of consecutive output rows (transform)
 };
 
 hipError_t launch_zero_counters(int *c, int n, hipStream_t s);
@@ -128,6 +128,11 @@ struct LaunchEvents {
     hipEvent_t start = nullptr;
     hipEvent_t stop = nullptr;
 };
+
+// LDS bytes of the runtime-radix kernels for padded length L: the buffer
+// holds L rounded up to 16 elements (the first-pass slot map stays inside
+// aligned blocks of 16).
+inline size_t generic_lds_bytes(int L) { return (size_t)((L + 15) & ~15) * 8; }
 
 hipError_t launch_generate(const GenParams &p, int total_bins, hipStream_t s);
 hipError_t launch_forward(const FwdParams &p, hipStream_t s);

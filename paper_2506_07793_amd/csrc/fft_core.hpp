@@ -206,6 +206,13 @@ struct Dft<5, SIGN> : DftOdd<5, SIGN> {};
 template <int SIGN>
 struct Dft<7, SIGN> : DftOdd<7, SIGN> {};
 
+// LDS slot of element i in the buffer between the first and the second pass
+// of a plan whose first radix is even: the low four bits are XORed with bits
+// 4-7, so that the first pass's scatter to R j + r (R even) reaches 16
+// distinct banks per 16-lane write group.  Stays inside i's aligned block of
+// 16, so a buffer of L rounded up to 16 elements holds every slot.
+__device__ __forceinline__ int first_pass_slot(int i) { return i ^ ((i >> 4) & 15); }
+
 // Butterflies a thread may hold at once in one pass when it holds at most
 // MAXV complex values.
 template <int R, int MAXV>
@@ -252,11 +259,18 @@ __device__ __attribute__((noinline)) void stockham_pass(int L, int Ns, int T, in
         }
     }
     if (SYNC_MID) __syncthreads();
+    // jm = j mod Ns for j = tid + k T, stepped by T mod Ns (one division per
+    // pass instead of one per butterfly)
+    const int dT = T % Ns;
+    int jm = tid % Ns;
 #pragma unroll
     for (int k = 0; k < MB; ++k) {
         const int j = tid + k * T;
+        if (k > 0) {
+            jm += dT;
+            if (jm >= Ns) jm -= Ns;
+        }
         if (j < S) {
-            const int jm = j % Ns;
             if (Ns > 1) {
                 cf w[R];
                 twiddle_powers<R>(conj_if<SIGN>(tw[(unsigned)(jm * twstep)]), w);
