@@ -26,6 +26,32 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_fixed_main_64ch_4096x100f_complex64.md")
+
+
+def committed_traffic(plan, out):
+    """HBM bytes per transform launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
+    kernel sources no longer hash to the profiled ones or the workload
+    differs from the profiled one."""
+    import hashlib
+    if plan.desc.kernel != 1 or out != "complex64" or not os.path.exists(PROFILE):
+        return None
+    fields = {}
+    for line in open(PROFILE):
+        k, _, v = line.strip().partition(": ")
+        if k in ("traffic_bytes_per_launch", "kernel_sources_sha256", "kernel_sources"):
+            fields[k] = v.strip()
+    if len(fields) != 3:
+        return None
+    h = hashlib.sha256()
+    for rel in fields["kernel_sources"].split():
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    if h.hexdigest() != fields["kernel_sources_sha256"]:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def kernel_name(plan):
     """The transform kernel the plan launches (the one the roofline prices)."""
     if plan.desc.kernel == 1:
@@ -367,8 +393,10 @@ def main():
                    "launch": "hip graph replay" if args.graph else "direct"},
         "roofline": {"bound": "hbm", "kernel": kernel_name(plan),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes": main_bytes, "avg_ms": ms_main},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(plan, args.out),
+                     "algorithmic_bytes": main_bytes, "avg_ms": ms_main,
+                     "median_ms": float(np.median(kernel_ms)),
+                     "p90_ms": float(np.percentile(kernel_ms, 90))},
         "step_hbm_frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "store_ceiling": {"kernel": "torch fill_ of the output buffer",
                           "GBps": out.numel() * out.element_size() / (ms_fill * 1e-3) / 1e9,
