@@ -6,12 +6,15 @@ Workload (one step = the whole hot path on one batch, inputs resident in HBM):
 10 Hz alpha bursts, seed 2), 100 log-spaced frequencies 1-100 Hz,
 n_cycles = clip(f/2, 3, 10), FP32 input, complex64 output [64, 100, 4096]:
 forward real FFT of every channel, then per (channel, frequency) the spectral
-multiply, inverse FFT, crop and store.
+multiply, inverse FFT, crop and store.  By default the K timed steps run as
+cwt_execute_batches: one launch per step that transforms the step's batch and
+computes the next batch's forward FFT (--serial: forward + transform launches
+per step; the serial step time is reported either way).
 
 Prints one JSON line with the throughput (output samples x frequencies per
-second), the roofline of the dominant kernel (the fused multiply/inverse-FFT
-kernel, timed with HIP events on its own stream inside the timed region) and
-the FP64 CPU oracle's throughput on a bounded sample of the same workload.
+second), the roofline of the dominant kernel (the transform launch, each timed
+by events bound to its own dispatch on the stream it runs on) and the FP64
+CPU oracle's throughput on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -26,19 +29,23 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_fixed_main_64ch_4096x100f_complex64.md")
+PROFILES = {
+    "fused": os.path.join(ROOT, "profiles", "k_fixed_fused_64ch_4096x100f_complex64.md"),
+    "main": os.path.join(ROOT, "profiles", "k_fixed_main_64ch_4096x100f_complex64.md"),
+}
 
 
-def committed_traffic(plan, out):
-    """HBM bytes per transform launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
-    kernel sources no longer hash to the profiled ones or the workload
+def committed_traffic(plan, out, kind):
+    """HBM bytes per launch of the timed kernel from its committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
+    the kernel sources no longer hash to the profiled ones or the workload
     differs from the profiled one."""
     import hashlib
-    if plan.desc.kernel != 1 or out != "complex64" or not os.path.exists(PROFILE):
+    path = PROFILES.get(kind)
+    if plan.desc.kernel != 1 or out != "complex64" or not path or not os.path.exists(path):
         return None
     fields = {}
-    for line in open(PROFILE):
+    for line in open(path):
         k, _, v = line.strip().partition(": ")
         if k in ("traffic_bytes_per_launch", "kernel_sources_sha256", "kernel_sources"):
             fields[k] = v.strip()
@@ -52,8 +59,11 @@ def committed_traffic(plan, out):
     return int(fields["traffic_bytes_per_launch"])
 
 
-def kernel_name(plan):
-    """The transform kernel the plan launches (the one the roofline prices)."""
+def kernel_name(plan, fused):
+    """The transform kernel the timed steps launch (the one the roofline prices)."""
+    if plan.desc.kernel == 1 and fused:
+        return ("k_fixed_fused (multiply + inverse FFT + store of one batch, forward FFT of "
+                "the next, register-resident, L=%d)" % plan.L)
     if plan.desc.kernel == 1:
         return "k_fixed_main (multiply + inverse FFT + store, register-resident, L=%d)" % plan.L
     return "k_main (multiply + inverse FFT + store, runtime radices, L=%d)" % plan.L
@@ -63,12 +73,14 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--out", default="complex64", choices=["complex64", "power"])
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing (profiling runs)")
     ap.add_argument("--cpu-channels", type=int, default=64,
                     help="channels of the oracle's timed sample (all 100 frequencies each)")
+    ap.add_argument("--serial", action="store_true",
+                    help="time K forward + transform pairs instead of the pipelined form")
     ap.add_argument("--graph", type=int, default=0,
                     help="1: replay the step as a captured HIP graph; 0: direct launches (default)")
     ap.add_argument("--batch-steps", type=int, default=3,
@@ -305,72 +317,100 @@ def main():
         plan.forward_spectra(x, ws, stream=stream)
         plan.transform_spectra(C, out, ws, stream=stream)
 
+    # Pipelined form (cwt_execute_batches): one launch per step that
+    # transforms this step's batch and computes the next batch's forward FFT
+    # into the other half of a double-buffered workspace.  Every step still
+    # runs the whole path on one batch; the batches are the same resident
+    # input (stride 0) and overwrite one output buffer (stride 0).
+    wsb = plan.alloc_batches_workspace(C, device=dev)
+
+    def batches(n):
+        plan.execute_batches(x, n, out, wsb, C, x_batch_stride=0, out_batch_stride=0,
+                             stream=stream)
+
+    def timed(fn):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1)
+
     K = args.steps
+    serial = not args.graph and args.serial
     with torch.cuda.stream(stream):
         for _ in range(args.warmup):
             step()
+        batches(args.warmup)
         torch.cuda.synchronize()
 
-        # The timed region: K steps, as direct launches or a replayed HIP graph.
-        # Each transform launch of the direct timed region carries a pair of
-        # events bound to its own dispatch (cwt_plan_timing_start; the events
-        # have no system-scope fence, so they add no cache write-back), which
-        # gives the kernel's average launch duration on the stream it runs on
-        # from the very launches being timed.  A graph cannot carry them:
-        # with --graph the kernel is timed on K direct steps first.
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        run = step
-        kernel_ms = None
+        # Serial reference first (forward + transform per step, no
+        # pipelining), so that the timed region runs on a warm device.
+        ms_serial = timed(lambda: [step() for _ in range(K)]) / K
+
+        # The timed region: K steps.  Default: K pipelined steps (one
+        # cwt_execute_batches call); --serial: K forward + transform pairs;
+        # --graph 1: K replays of a captured forward + transform step.
         if args.graph:
-            plan.timing_start(K)
-            for _ in range(K):
-                step()
-            torch.cuda.synchronize()
-            kernel_ms = plan.timing_stop()
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g, stream=stream):
                 step()
             for _ in range(args.warmup):
                 g.replay()
-            run = g.replay
+
+            def region():
+                for _ in range(K):
+                    g.replay()
+        elif serial:
+            def region():
+                for _ in range(K):
+                    step()
         else:
-            plan.timing_start(K)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        for _ in range(K):
-            run()
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ms_step = ev0.elapsed_time(ev1) / K
-        if kernel_ms is None:
-            kernel_ms = plan.timing_stop()
+            def region():
+                batches(K)
+        ms_step = timed(region) / K
+
+        # The kernel's launch durations: the same K steps once more, each
+        # transform launch carrying a pair of events bound to its own
+        # dispatch (cwt_plan_timing_start; no system-scope fence, so no
+        # cache write-back), on the stream it runs on.  They widen the gap
+        # between launches by about a microsecond, which is why the step
+        # time above comes from a pass without them.  (A graph cannot carry
+        # them: with --graph the kernel is timed on direct steps.)
+        plan.timing_start(K)
+        if args.graph or serial:
+            ms_step_ev = timed(lambda: [step() for _ in range(K)]) / K
+        else:
+            ms_step_ev = timed(lambda: batches(K)) / K
+        kernel_ms = plan.timing_stop()
         assert len(kernel_ms) == K, "timed %d of %d transform launches" % (len(kernel_ms), K)
+        fused = not (args.graph or serial) and plan.desc.kernel == 1 and K > 1
+        if fused:
+            kernel_ms = kernel_ms[:-1]  # the last step has no next batch to fuse
         ms_main = float(np.mean(kernel_ms))
 
         # Store ceiling: a plain device fill of the same output buffer.
         fill = out.view(torch.float32)
         for _ in range(3):
             fill.fill_(0.0)
-        ev0.record(stream)
-        for _ in range(K):
-            fill.fill_(0.0)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ms_fill = ev0.elapsed_time(ev1) / K
+        ms_fill = timed(lambda: [fill.fill_(0.0) for _ in range(K)]) / K
 
     pts = C * F * N
     value = pts / (ms_step * 1e-3)
     desc = plan.desc
     elem = 8 if args.out == "complex64" else 4
     Lh = plan.L // 2 + 1
-    # Algorithmic bytes of one launch of the fused transform kernel: every
-    # output element written once, every channel half-spectrum and every
-    # stored wavelet-spectrum bin read once.
-    main_bytes = pts * elem + C * Lh * 8 + int(desc.spectrum_bins) * 4
+    # Algorithmic bytes of one launch of the transform kernel: every output
+    # element written once, every channel half-spectrum and every stored
+    # wavelet-spectrum bin read once; the pipelined launch also reads the
+    # next batch's signal and writes its half spectra once.
+    transform_bytes = pts * elem + C * Lh * 8 + int(desc.spectrum_bins) * 4
+    main_bytes = transform_bytes + (C * N * 4 + C * Lh * 8 if fused else 0)
     achieved = main_bytes / (ms_main * 1e-3) / 1e9
     # Whole step: the input signal and the spectra round trip as well.
-    step_bytes = main_bytes + C * N * 4 + C * Lh * 8
+    step_bytes = pts * elem + C * Lh * 8 + int(desc.spectrum_bins) * 4 + C * N * 4 + C * Lh * 8
 
     result = {
         "metric": "CWT output samples x freqs per second (+ %HBM roofline; p99 stream window "
@@ -390,14 +430,19 @@ def main():
                                "n_cycles=clip(f/2,3,10), FP32 in, %s out" % args.out,
                    "channels": C, "samples": N, "freqs": F, "padded_len": plan.L,
                    "radices": plan.radices, "out": args.out,
-                   "launch": "hip graph replay" if args.graph else "direct"},
-        "roofline": {"bound": "hbm", "kernel": kernel_name(plan),
+                   "launch": ("hip graph replay of forward + transform" if args.graph else
+                              "forward + transform per step" if serial else
+                              "pipelined: one launch per step (transform + next forward)")},
+        "roofline": {"bound": "hbm", "kernel": kernel_name(plan, fused),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": committed_traffic(plan, args.out),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": committed_traffic(plan, args.out, "fused" if fused else "main"),
                      "algorithmic_bytes": main_bytes, "avg_ms": ms_main,
                      "median_ms": float(np.median(kernel_ms)),
                      "p90_ms": float(np.percentile(kernel_ms, 90))},
         "step_hbm_frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "ms_per_step_with_timing_events": ms_step_ev,
+        "serial_steps": {"ms_per_step": ms_serial, "value": pts / (ms_serial * 1e-3)},
         "store_ceiling": {"kernel": "torch fill_ of the output buffer",
                           "GBps": out.numel() * out.element_size() / (ms_fill * 1e-3) / 1e9,
                           "ms": ms_fill},
@@ -421,7 +466,7 @@ def main():
             ms_p = float(np.mean(pp.timing_stop()))
         prec_runs.append({"precision": prec, "transform_ms": ms_p,
                           "transform_pts_per_s": pts / (ms_p * 1e-3),
-                          "hbm_frac": main_bytes / (ms_p * 1e-3) / 1e9 / HBM_PEAK_GBS})
+                          "hbm_frac": transform_bytes / (ms_p * 1e-3) / 1e9 / HBM_PEAK_GBS})
         pp.close()
     result["precision_variants"] = prec_runs
 

@@ -227,6 +227,31 @@ int cwt_plan_copy_tables(const cwt_plan *plan, float *H_host, int32_t *band_host
 int cwt_plan_timing_start(cwt_plan *plan, int32_t max_launches);
 int cwt_plan_timing_stop(cwt_plan *plan, float *ms_host, int32_t max, int32_t *n_out);
 
+/*
+ * Throughput form of cwt_execute for n_batches batches of C channels with the
+ * same plan, such as consecutive windows of a long recording or recordings
+ * of equal shape (section "Comparison between devices and software" runs the
+ * transform over and over).  Batch i reads x + i * x_batch_stride floats and
+ * writes out + i * out_batch_stride bytes, with the layouts of cwt_execute; a
+ * stride of 0 reuses one buffer (each batch then overwrites the previous
+ * batch's output).  Everything runs on `stream`, in batch order.  With a
+ * register-resident transform kernel (cwt_plan_desc.kernel == 1) each batch
+ * is one launch that also computes the forward FFT of the next batch into
+ * the other half of a double-buffered workspace; other plans run
+ * cwt_execute's two stages per batch.  Results equal cwt_execute's bit for
+ * bit.  ws: device, at least cwt_batches_workspace_size(plan, C) bytes,
+ * 256-byte aligned.  The x of every batch, the out of every batch and ws must
+ * not overlap; out_batch_stride must be a multiple of 8.  n_batches == 0 or
+ * C == 0 is a no-op.  Errors: those of cwt_execute, CWT_E_INVALID for
+ * n_batches < 0, a negative stride or a workspace under twice
+ * cwt_workspace_size (on an error after the first launch, earlier batches
+ * stay queued).
+ */
+size_t cwt_batches_workspace_size(const cwt_plan *plan, int64_t C);
+int cwt_execute_batches(const cwt_plan *plan, const float *x, int64_t x_batch_stride,
+                        int32_t n_batches, int64_t C, void *out, int64_t out_batch_stride,
+                        void *ws, size_t ws_bytes, void *stream);
+
 /* ---- batches ---------------------------------------------------------- */
 /*
  * Many recordings at once, each with its own plan (length, sampling rate,

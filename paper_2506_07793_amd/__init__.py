@@ -132,6 +132,30 @@ class Plan:
             tw.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream_handle(stream)))
         return H[: int(self.desc.spectrum_bins)], band, tw.view(np.complex64)
 
+    def batches_workspace_size(self, C):
+        return int(self._lib.cwt_batches_workspace_size(self._ptr, int(C)))
+
+    def alloc_batches_workspace(self, C, device="cuda"):
+        """Double-buffered workspace for execute_batches."""
+        import torch
+        nbytes = max(256, self.batches_workspace_size(C))
+        return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+    def execute_batches(self, x, n_batches, out, ws, C, x_batch_stride=None,
+                        out_batch_stride=None, stream=None):
+        """n_batches batches of C channels (cwt_execute_batches): batch i
+        reads x at i * x_batch_stride floats and writes out at
+        i * out_batch_stride bytes (defaults: consecutive batches)."""
+        if x_batch_stride is None:
+            x_batch_stride = int(C) * self.n
+        if out_batch_stride is None:
+            out_batch_stride = self.output_bytes(C)
+        _lib.check(self._lib.cwt_execute_batches(
+            self._ptr, _dptr(x), int(x_batch_stride), int(n_batches), int(C), _dptr(out),
+            int(out_batch_stride), _dptr(ws), ws.numel() * ws.element_size(),
+            _stream_handle(stream)))
+        return out
+
     def timing_start(self, max_launches):
         """Bind dispatch-timed event pairs to the next max_launches transform
         launches of this plan (cwt_plan_timing_start)."""
@@ -164,6 +188,10 @@ class Plan:
     # -- execution -------------------------------------------------------
     def output_shape(self, C):
         return (int(C), self.out_rows, self.n)
+
+    def output_bytes(self, C):
+        elem = 8 if self.out_mode == "complex64" else 4
+        return int(C) * self.out_rows * self.n * elem
 
     def output_bytes(self, C):
         elem = 8 if self.out_mode == "complex64" else 4

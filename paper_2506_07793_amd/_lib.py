@@ -132,6 +132,8 @@ SIGNATURES = {
     "cwt_plan_destroy": (ctypes.c_int, [_VP, _VP]),
     "cwt_plan_autotune": (ctypes.c_int, [_VP, _I64, _VP, ctypes.POINTER(TuneResult)]),
     "cwt_plan_timing_start": (ctypes.c_int, [_VP, _I32]),
+    "cwt_batches_workspace_size": (_SZ, [_VP, _I64]),
+    "cwt_execute_batches": (ctypes.c_int, [_VP, _VP, _I64, _I32, _I64, _VP, _I64, _VP, _SZ, _VP]),
     "cwt_plan_timing_stop": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float), _I32,
                                             ctypes.POINTER(_I32)]),
     "cwt_batch_workspace_size": (_SZ, [ctypes.POINTER(BatchItem), _I32]),

@@ -547,7 +547,7 @@ extern "C" size_t cwt_workspace_size(const cwt_plan *P, int64_t C)
 
 // Validation shared by cwt_execute and its two stages.  x_needed / out_needed
 // say which device pointers the call uses.
-static int check_exec_args(const cwt_plan *P, const float *x, bool x_needed, int64_t C,
+int check_exec_args(const cwt_plan *P, const float *x, bool x_needed, int64_t C,
                            void *out, bool out_needed, void *ws, size_t ws_bytes)
 {
     if (!P) return fail(CWT_E_INVALID, "plan is NULL");

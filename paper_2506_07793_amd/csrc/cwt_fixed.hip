@@ -252,11 +252,9 @@ __device__ __forceinline__ void band_transform(const cf *__restrict__ X,
 
 // ------------------------------------------------------------ inverse --
 
+// One output row (channel, frequency or band) item of the transform.
 template <int MODE, int TWM, int... Rs>
-__global__ void __launch_bounds__(RList<Rs...>::product / kV)
-    __attribute__((amdgpu_waves_per_eu(
-        (MODE != kOutBand && RList<Rs...>::product == 4096) ? 5 : 1)))
-    k_fixed_main(MainParams p)
+__device__ __forceinline__ void fixed_main_row(const MainParams &p, int item)
 {
     using RL = RList<Rs...>;
     constexpr int L = RL::product;
@@ -267,8 +265,8 @@ __global__ void __launch_bounds__(RList<Rs...>::product / kV)
     const int N = p.N;
     const cf *tw = reinterpret_cast<const cf *>(p.tw);
 
-    const int c = blockIdx.x / p.n_rows;
-    const int row = blockIdx.x - c * p.n_rows;
+    const int c = item / p.n_rows;
+    const int row = item - c * p.n_rows;
     int qb, qe;
     if (MODE == kOutBand) {
         qb = p.grp_off[row];
@@ -347,20 +345,35 @@ __global__ void __launch_bounds__(RList<Rs...>::product / kV)
     }
 }
 
+// Occupancy of the transform kernels: 5 waves per SIMD for L = 4096 (the LDS
+// of 5 workgroups fills the CU), no constraint otherwise.
+template <int MODE, int L>
+struct FixedWaves {
+    static constexpr int value = (MODE != kOutBand && L == 4096) ? 5 : 1;
+};
+
+template <int MODE, int TWM, int... Rs>
+__global__ void __launch_bounds__(RList<Rs...>::product / kV)
+    __attribute__((amdgpu_waves_per_eu(FixedWaves<MODE, RList<Rs...>::product>::value)))
+    k_fixed_main(MainParams p)
+{
+    fixed_main_row<MODE, TWM, Rs...>(p, blockIdx.x);
+}
+
 // ------------------------------------------------------------ forward --
 // Two real channels packed as one complex sequence, forward transform in
 // registers, then the separation X0 = (Z[b] + conj Z[-b]) / 2,
 // X1 = (Z[b] - conj Z[-b]) / (2i) through LDS.
 
 template <int... Rs>
-__global__ void __launch_bounds__(RList<Rs...>::product / kV) k_fixed_forward(FwdParams p)
+__device__ __forceinline__ void fixed_forward_pair(const FwdParams &p, int pair)
 {
     using RL = RList<Rs...>;
     constexpr int L = RL::product;
     constexpr int T = L / kV;
     extern __shared__ cf lds[];
     const int t = threadIdx.x;
-    const int c0 = 2 * blockIdx.x;
+    const int c0 = 2 * pair;
     const bool has1 = (c0 + 1) < p.C;
     const float *x0 = p.x + (int64_t)c0 * p.x_stride;
     const float *x1 = p.x + (int64_t)(c0 + 1) * p.x_stride;
@@ -392,6 +405,28 @@ __global__ void __launch_bounds__(RList<Rs...>::product / kV) k_fixed_forward(Fw
         X0[b] = make_float2(0.5f * s.x, 0.5f * s.y);
         if (has1) X1[b] = make_float2(0.5f * d.y, -0.5f * d.x);
     }
+}
+
+template <int... Rs>
+__global__ void __launch_bounds__(RList<Rs...>::product / kV) k_fixed_forward(FwdParams p)
+{
+    fixed_forward_pair<Rs...>(p, blockIdx.x);
+}
+
+// Transform of one batch and forward FFT of the next in one launch: blocks
+// [0, n_fwd) take the forward role (channel pairs of the next batch, into the
+// other half of the workspace) and start first, the rest the transform rows,
+// so the short forward work runs beside the transform instead of between two
+// launches.
+template <int MODE, int TWM, int... Rs>
+__global__ void __launch_bounds__(RList<Rs...>::product / kV)
+    __attribute__((amdgpu_waves_per_eu(FixedWaves<MODE, RList<Rs...>::product>::value)))
+    k_fixed_fused(MainParams p, FwdParams f, int n_fwd)
+{
+    if ((int)blockIdx.x < n_fwd)
+        fixed_forward_pair<Rs...>(f, blockIdx.x);
+    else
+        fixed_main_row<MODE, TWM, Rs...>(p, blockIdx.x - n_fwd);
 }
 
 template <int... Rs>
@@ -451,6 +486,55 @@ static hipError_t launch_fixed_modes(const MainParams &p, hipStream_t s, LaunchE
 {
     return p.variant == 1 ? launch_fixed_modes_t<kTwPowers, Rs...>(p, s, ev)
                           : launch_fixed_modes_t<kTwTable, Rs...>(p, s, ev);
+}
+
+template <int MODE, int TWM, int... Rs>
+static hipError_t launch_fused_t(const MainParams &p, const FwdParams &f, hipStream_t s,
+                                 LaunchEvents ev)
+{
+    constexpr int L = RList<Rs...>::product;
+    const size_t lds = (size_t)L * sizeof(cf);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_fixed_fused<MODE, TWM, Rs...>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        attr_set = true;
+    }
+    const int n_fwd = (f.C + 1) / 2;
+    hipExtLaunchKernelGGL((k_fixed_fused<MODE, TWM, Rs...>), dim3(n_fwd + p.C * p.n_rows),
+                          dim3(L / kV), lds, s, ev.start, ev.stop, 0, p, f, n_fwd);
+    return hipGetLastError();
+}
+
+template <int TWM, int... Rs>
+static hipError_t launch_fused_modes_t(const MainParams &p, const FwdParams &f, hipStream_t s,
+                                       LaunchEvents ev)
+{
+    switch (p.out_mode) {
+    case kOutComplex: return launch_fused_t<kOutComplex, TWM, Rs...>(p, f, s, ev);
+    case kOutPower: return launch_fused_t<kOutPower, TWM, Rs...>(p, f, s, ev);
+    default: return launch_fused_t<kOutBand, TWM, Rs...>(p, f, s, ev);
+    }
+}
+
+template <int... Rs>
+static hipError_t launch_fused_modes(const MainParams &p, const FwdParams &f, hipStream_t s,
+                                     LaunchEvents ev)
+{
+    return p.variant == 1 ? launch_fused_modes_t<kTwPowers, Rs...>(p, f, s, ev)
+                          : launch_fused_modes_t<kTwTable, Rs...>(p, f, s, ev);
+}
+
+hipError_t launch_fused_fixed(const MainParams &p, const FwdParams &f, hipStream_t s,
+                              LaunchEvents ev)
+{
+    switch (p.rp.L) {
+    case 1024: return launch_fused_modes<16, 16, 4>(p, f, s, ev);
+    case 2048: return launch_fused_modes<16, 16, 8>(p, f, s, ev);
+    case 4096: return launch_fused_modes<16, 16, 16>(p, f, s, ev);
+    case 8192: return launch_fused_modes<16, 16, 16, 2>(p, f, s, ev);
+    default: return hipErrorNotSupported;
+    }
 }
 
 bool fixed_main_available(int L)

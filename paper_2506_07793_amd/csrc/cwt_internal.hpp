@@ -80,3 +80,7 @@ int enqueue_execute_split(const cwt_plan &P, const float *x, int64_t C, int64_t 
 int enqueue_transform_split(const cwt_plan &P, int64_t C, void *out, void *ws, hipStream_t s);
 
 }  // namespace cwtrt
+
+// Argument checks shared by the execute entry points (sets the error message).
+int check_exec_args(const cwt_plan *P, const float *x, bool x_needed, int64_t C, void *out,
+                    bool out_needed, void *ws, size_t ws_bytes);

@@ -141,5 +141,8 @@ hipError_t launch_main(const MainParams &p, hipStream_t s, LaunchEvents ev = {})
 bool fixed_main_available(int L);
 hipError_t launch_main_fixed(const MainParams &p, hipStream_t s, LaunchEvents ev = {});
 hipError_t launch_forward_fixed(const FwdParams &p, hipStream_t s);
+// Transform of p's spectra and forward FFT f of the next batch in one launch.
+hipError_t launch_fused_fixed(const MainParams &p, const FwdParams &f, hipStream_t s,
+                              LaunchEvents ev = {});
 
 }  // namespace cwtk

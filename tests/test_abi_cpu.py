@@ -143,6 +143,9 @@ def test_validation_raw_abi():
     n = ctypes.c_int32(-1)
     assert lib.cwt_plan_timing_start(None, 4) == _lib.CWT_E_INVALID
     assert lib.cwt_plan_timing_stop(None, None, 0, ctypes.byref(n)) == _lib.CWT_E_INVALID
+    # batches of one plan: NULL plan rejected, no workspace for it
+    assert lib.cwt_execute_batches(None, None, 0, 1, 1, None, 0, None, 0, None) == _lib.CWT_E_INVALID
+    assert lib.cwt_batches_workspace_size(None, 4) == 0
 
 
 def test_band_membership_rule():

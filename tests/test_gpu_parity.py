@@ -377,3 +377,49 @@ def test_band_path_edges(L, out):
         assert e <= TOL_P
     plan.close()
 
+
+
+@pytest.mark.parametrize("n,precision,out", [(4096, "fp32", "complex64"), (4096, "fp32", "bandpower"),
+                                             (1000, "fp32", "power"), (4096, "split_bf16", "complex64"),
+                                             (1000, "fp32", "complex64")])
+def test_execute_batches_matches_execute(n, precision, out):
+    """cwt_execute_batches gives, batch for batch, exactly cwt_execute's
+    output: with the register-resident kernel (L = 4096, transform of one
+    batch and forward FFT of the next in one launch), with the runtime-radix
+    kernel (L = 1000) and with the split-precision path; a zero stride reuses
+    one buffer; n_batches = 0 is a no-op; bad arguments are rejected."""
+    C, nb = 3, 5
+    d = synth.eeg_64ch(C=C * nb, N=n, F=40)
+    x = torch.from_numpy(d["x"]).cuda().view(nb, C, -1)
+    plan = cwt.Plan(n, d["sfreq"], d["freqs"], n_cycles=d["n_cycles"], precision=precision,
+                    out=out)
+    assert plan.desc.kernel == (1 if n == 4096 else 0)
+    refs = [plan.execute(x[i]).clone() for i in range(nb)]
+    outb = torch.stack([torch.empty_like(refs[0]) for _ in range(nb)])
+    ws = plan.alloc_batches_workspace(C)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.execute_batches(x, nb, outb, ws, C, stream=s)
+    torch.cuda.synchronize()
+    for i in range(nb):
+        assert torch.equal(outb[i], refs[i]), "batch %d differs" % i
+    one = torch.empty_like(refs[0])
+    plan.execute_batches(x[0], 4, one, ws, C, x_batch_stride=0, out_batch_stride=0)
+    torch.cuda.synchronize()
+    assert torch.equal(one, refs[0])
+    one.zero_()
+    plan.execute_batches(x, 0, one, ws, C)
+    torch.cuda.synchronize()
+    assert not one.abs().any()
+    from paper_2506_07793_amd import _lib
+    lib = _lib.load()
+    import ctypes
+    vp = ctypes.c_void_p
+    args = (vp(x.data_ptr()), C * n, 2, C, vp(outb.data_ptr()))
+    assert lib.cwt_execute_batches(plan.handle, *args, 12, vp(ws.data_ptr()), ws.numel(),
+                                   None) == _lib.CWT_E_INVALID  # stride not a multiple of 8
+    assert lib.cwt_execute_batches(plan.handle, *args, plan.output_bytes(C), vp(ws.data_ptr()),
+                                   ws.numel() // 2, None) == _lib.CWT_E_INVALID  # one half only
+    assert lib.cwt_execute_batches(plan.handle, vp(x.data_ptr()), -1, 2, C, vp(outb.data_ptr()),
+                                   0, vp(ws.data_ptr()), ws.numel(), None) == _lib.CWT_E_INVALID
+    plan.close()
