@@ -16,6 +16,8 @@ Paper sections followed:
   * Morlet / Gabor Fourier-domain equations (same section) for Psi_hat; the
     constants c and kappa, which the paper leaves implicit, are the unit-energy
     and zero-mean closed forms (see ``cwt_oracle.c``).
+  * The generalized Morse wavelet equation (same section), read with the unit
+    step for sign(omega) and alpha = 2 (e gamma / beta)^(beta / gamma).
   * "Fast Fourier transform": pad to the smallest 2*3*5*7-smooth length >= N.
   * "Precision": power |W|^2 and the real/imag/phase comparison metric.
   * Introduction: the EEG bands delta/theta/alpha/beta/gamma (edges are a
@@ -35,6 +37,11 @@ from . import build as _build
 
 MORLET = 0
 GABOR = 1
+GMW = 2
+
+#: Generalized Morse wavelet parameters the paper uses (section "Precision").
+GMW_BETA = 17.5
+GMW_GAMMA = 3.0
 
 #: EEG bands named in the paper's introduction; the edges (Hz) are a reading:
 #: lo <= f < hi, except that the last band also includes f == hi.
@@ -57,6 +64,12 @@ def _configure(lib):
     lib.orc_mother_spectrum.argtypes = [ctypes.c_int, dbl, dbl]
     lib.orc_wavelet_spectrum.restype = None
     lib.orc_wavelet_spectrum.argtypes = [i64, dbl, dbl, dbl, ctypes.c_int, p_d]
+    lib.orc_gmw_peak.restype = dbl
+    lib.orc_gmw_peak.argtypes = [dbl, dbl]
+    lib.orc_gmw_spectrum.restype = dbl
+    lib.orc_gmw_spectrum.argtypes = [dbl, dbl, dbl]
+    lib.orc_gmw_wavelet_spectrum.restype = None
+    lib.orc_gmw_wavelet_spectrum.argtypes = [i64, dbl, dbl, dbl, dbl, p_d]
     lib.orc_idft_real_spectrum.restype = None
     lib.orc_idft_real_spectrum.argtypes = [i64, p_d, p_d, p_d]
     lib.orc_cwt_rows.restype = None
@@ -86,6 +99,8 @@ def _kind(kind):
         return MORLET
     if kind in (GABOR, "gabor"):
         return GABOR
+    if kind in (GMW, "gmw"):
+        return GMW
     raise ValueError("unknown wavelet kind %r" % (kind,))
 
 
@@ -125,6 +140,20 @@ def mother_spectrum(sigma, u, kind=MORLET):
     return np.array([lib.orc_mother_spectrum(_kind(kind), float(sigma), float(v)) for v in u])
 
 
+def gmw_peak(beta=GMW_BETA, gamma=GMW_GAMMA):
+    """u_p = (beta / gamma)^(1 / gamma), where the GMW spectrum peaks."""
+    return float(_load().orc_gmw_peak(float(beta), float(gamma)))
+
+
+def gmw_spectrum(u, beta=GMW_BETA, gamma=GMW_GAMMA):
+    """Generalized Morse wavelet in the Fourier domain (GMW equation of
+    "Fourier transformed formula", read with the unit step and the peak-2
+    normalisation alpha = 2 (e gamma / beta)^(beta / gamma))."""
+    lib = _load()
+    u = np.atleast_1d(np.asarray(u, dtype=np.float64))
+    return np.array([lib.orc_gmw_spectrum(float(beta), float(gamma), float(v)) for v in u])
+
+
 def sigmas_for(freqs, n_cycles):
     """n_cycles is one number (the paper's sigma) or one value per frequency."""
     freqs = np.asarray(freqs, dtype=np.float64)
@@ -136,19 +165,25 @@ def sigmas_for(freqs, n_cycles):
     return s
 
 
-def wavelet_spectrum(L, sfreq, f, sigma, kind=MORLET):
-    """H_f[b], b in [0, L): the scaled Fourier-domain wavelet on the DFT bins."""
+def wavelet_spectrum(L, sfreq, f, sigma, kind=MORLET, beta=GMW_BETA, gamma=GMW_GAMMA):
+    """H_f[b], b in [0, L): the scaled Fourier-domain wavelet on the DFT bins
+    (sigma for Morlet / Gabor; beta and gamma for the GMW)."""
     H = np.empty(int(L), dtype=np.float64)
-    _load().orc_wavelet_spectrum(int(L), float(sfreq), float(f), float(sigma), _kind(kind),
-                                 _ptr(H))
+    if _kind(kind) == GMW:
+        _load().orc_gmw_wavelet_spectrum(int(L), float(sfreq), float(f), float(beta),
+                                         float(gamma), _ptr(H))
+    else:
+        _load().orc_wavelet_spectrum(int(L), float(sfreq), float(f), float(sigma), _kind(kind),
+                                     _ptr(H))
     return H
 
 
-def wavelet_bank(L, sfreq, freqs, n_cycles, kind=MORLET):
+def wavelet_bank(L, sfreq, freqs, n_cycles, kind=MORLET, beta=GMW_BETA, gamma=GMW_GAMMA):
     """[F, L] spectra for every analysis frequency."""
     freqs = np.asarray(freqs, dtype=np.float64)
-    sig = sigmas_for(freqs, n_cycles)
-    return np.stack([wavelet_spectrum(L, sfreq, f, s, kind) for f, s in zip(freqs, sig)])
+    sig = sigmas_for(freqs, n_cycles if _kind(kind) != GMW else 0.0)
+    return np.stack([wavelet_spectrum(L, sfreq, f, s, kind, beta, gamma)
+                     for f, s in zip(freqs, sig)])
 
 
 def wavelet_time(H):
@@ -162,12 +197,13 @@ def wavelet_time(H):
 
 
 def cwt(x, sfreq, freqs, n_cycles, kind=MORLET, pad="smooth7", L=None, rows=None, t0=0,
-        nt=None):
+        nt=None, beta=GMW_BETA, gamma=GMW_GAMMA):
     """Direct cyclic-convolution CWT in FP64.
 
     x: [C, N] (or [N]) real signal.  Returns complex128 [C, F, nt] with
     nt = N - t0 by default, or [len(rows), nt] when ``rows`` lists (c, f)
     index pairs.  ``L`` overrides the padded length (explicit padding).
+    For the GMW (kind "gmw") n_cycles is not used; beta and gamma are.
     """
     x = np.asarray(x, dtype=np.float64)
     if x.ndim == 1:
@@ -184,7 +220,7 @@ def cwt(x, sfreq, freqs, n_cycles, kind=MORLET, pad="smooth7", L=None, rows=None
         nt = N - t0
     if not (0 <= t0 and t0 + nt <= N):
         raise ValueError("output window outside [0, N)")
-    sig = sigmas_for(freqs, n_cycles)
+    sig = sigmas_for(freqs, n_cycles if _kind(kind) != GMW else 0.0)
     if rows is None:
         rc, rf = np.meshgrid(np.arange(C), np.arange(F), indexing="ij")
         rc, rf = rc.ravel(), rf.ravel()
@@ -195,7 +231,7 @@ def cwt(x, sfreq, freqs, n_cycles, kind=MORLET, pad="smooth7", L=None, rows=None
     h_re = np.zeros((F, L))
     h_im = np.zeros((F, L))
     for f in used:
-        h = wavelet_time(wavelet_spectrum(L, sfreq, freqs[f], sig[f], kind))
+        h = wavelet_time(wavelet_spectrum(L, sfreq, freqs[f], sig[f], kind, beta, gamma))
         h_re[f], h_im[f] = h.real, h.imag
     rc = np.ascontiguousarray(rc, dtype=np.int64)
     rf = np.ascontiguousarray(rf, dtype=np.int64)

@@ -28,6 +28,15 @@
  *     5. h[j] = (1/L) sum_b H[b] exp(+2 pi i (b j mod L) / L)   (direct IDFT)
  *     6. W[t] = sum_{k<N} x[k] h[(t - k) mod L],  t in [0, N)   (direct cyclic
  *        convolution; O(N L) per channel and frequency).
+ *
+ * Generalized Morse wavelet (same section, the GMW equation): the paper
+ * prints sign(omega) alpha omega^beta exp(-omega^gamma) with alpha "from
+ * beta and gamma".  Read here, as in Lilly and Olhede's analytic GMW, with
+ * the unit step U(omega) in place of sign(omega) (zero at omega <= 0) and
+ * alpha = 2 (e gamma / beta)^(beta / gamma), which makes the peak value 2 at
+ * u_p = (beta / gamma)^(1 / gamma).  The scale maps that peak to the analysis
+ * frequency: s = u_p / (2 pi f), and H[b] = sqrt(2 pi s sfreq) Psi_hat(s
+ * omega_b) as in step 4.
  */
 #include <math.h>
 #include <stdint.h>
@@ -39,6 +48,9 @@
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
+#endif
+#ifndef M_E
+#define M_E 2.71828182845904523536
 #endif
 
 /* ---- step 1: padded length ------------------------------------------- */
@@ -92,6 +104,16 @@ double orc_mother_spectrum(int kind, double sigma, double u)
     return c * pow(M_PI, -0.25) * (exp(-0.5 * a * a) - kappa * exp(-0.5 * u * u));
 }
 
+/* Generalized Morse wavelet in the Fourier domain (reading above). */
+double orc_gmw_peak(double beta, double gamma) { return pow(beta / gamma, 1.0 / gamma); }
+
+double orc_gmw_spectrum(double beta, double gamma, double u)
+{
+    if (u <= 0.0) return 0.0;
+    double alpha = 2.0 * pow(M_E * gamma / beta, beta / gamma);
+    return alpha * pow(u, beta) * exp(-pow(u, gamma));
+}
+
 /* ---- steps 3-4: sampled wavelet spectrum ------------------------------ */
 
 void orc_wavelet_spectrum(int64_t L, double sfreq, double f, double sigma, int kind,
@@ -103,6 +125,18 @@ void orc_wavelet_spectrum(int64_t L, double sfreq, double f, double sigma, int k
         int64_t bt = (2 * b < L) ? b : b - L;
         double omega = 2.0 * M_PI * sfreq * (double)bt / (double)L;
         H[b] = pref * orc_mother_spectrum(kind, sigma, s * omega);
+    }
+}
+
+void orc_gmw_wavelet_spectrum(int64_t L, double sfreq, double f, double beta, double gamma,
+                              double *H)
+{
+    double s = orc_gmw_peak(beta, gamma) / (2.0 * M_PI * f);
+    double pref = sqrt(2.0 * M_PI * s * sfreq);
+    for (int64_t b = 0; b < L; ++b) {
+        int64_t bt = (2 * b < L) ? b : b - L;
+        double omega = 2.0 * M_PI * sfreq * (double)bt / (double)L;
+        H[b] = pref * orc_gmw_spectrum(beta, gamma, s * omega);
     }
 }
 

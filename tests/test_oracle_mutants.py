@@ -45,13 +45,24 @@ PIN_CALLS = [
     (pins.test_cyclic_shift_equivariance, {}),
     (pins.test_dc_null_and_gabor_dc, {}),
     (pins.test_parseval, {}),
+    (pins.test_gmw_peak_is_two_at_closed_form_location, dict(beta=17.5, gamma=3.0)),
+    (pins.test_gmw_moments_match_gamma_functions, dict(beta=8.0, gamma=2.0)),
+    (pins.test_gmw_vanishes_at_nonpositive_frequencies, {}),
+    (pins.test_gmw_tone_closed_form, dict(beta=17.5, gamma=3.0)),
 ]
 
 MUTANTS = {
     "kappa_sign": ("- kappa * exp(-0.5 * u * u)", "+ kappa * exp(-0.5 * u * u)"),
     "c_constant": ("2.0 * exp(-0.75 * sigma * sigma)", "2.0 * exp(-0.5 * sigma * sigma)"),
-    "nyquist_sign": ("(2 * b < L) ? b : b - L", "(2 * b <= L) ? b : b - L"),
-    "dropped_2pi_prefactor": ("sqrt(2.0 * M_PI * s * sfreq)", "sqrt(s * sfreq)"),
+    "nyquist_sign": ("(2 * b < L) ? b : b - L;\n        double omega = 2.0 * M_PI * sfreq * (double)bt / (double)L;\n        H[b] = pref * orc_mother_spectrum",
+                     "(2 * b <= L) ? b : b - L;\n        double omega = 2.0 * M_PI * sfreq * (double)bt / (double)L;\n        H[b] = pref * orc_mother_spectrum"),
+    "gmw_nyquist_sign": ("(2 * b < L) ? b : b - L;\n        double omega = 2.0 * M_PI * sfreq * (double)bt / (double)L;\n        H[b] = pref * orc_gmw_spectrum",
+                         "(2 * b <= L) ? b : b - L;\n        double omega = 2.0 * M_PI * sfreq * (double)bt / (double)L;\n        H[b] = pref * orc_gmw_spectrum"),
+    "dropped_2pi_prefactor": ("sigma / (2.0 * M_PI * f);\n    double pref = sqrt(2.0 * M_PI * s * sfreq);",
+                              "sigma / (2.0 * M_PI * f);\n    double pref = sqrt(s * sfreq);"),
+    "gmw_dropped_2pi_prefactor": (
+        "orc_gmw_peak(beta, gamma) / (2.0 * M_PI * f);\n    double pref = sqrt(2.0 * M_PI * s * sfreq);",
+        "orc_gmw_peak(beta, gamma) / (2.0 * M_PI * f);\n    double pref = sqrt(s * sfreq);"),
     "scale_map": ("sigma / (2.0 * M_PI * f)", "sigma / (M_PI * f)"),
     "idft_direction": ("im += H[b] * sn[m];", "im -= H[b] * sn[m];"),
     "missing_1_over_L": ("h_re[j] = re / (double)L;", "h_re[j] = re;"),
@@ -61,6 +72,11 @@ MUTANTS = {
     "smooth_primes": ("{2, 3, 5, 7}", "{2, 3, 5, 11}"),
     "gabor_kappa": ("*kappa = 0.0;\n        *c = 1.0;", "*kappa = 0.0;\n        *c = 0.5;"),
     "exponent_half": ("exp(-0.5 * a * a)", "exp(-a * a)"),
+    "gmw_alpha_exponent": ("pow(M_E * gamma / beta, beta / gamma)",
+                           "pow(M_E * gamma / beta, gamma / beta)"),
+    "gmw_no_step": ("if (u <= 0.0) return 0.0;", "if (u < -1e300) return 0.0;"),
+    "gmw_peak_location": ("pow(beta / gamma, 1.0 / gamma)", "pow(beta / gamma, gamma)"),
+    "gmw_exponent_param": ("exp(-pow(u, gamma))", "exp(-pow(u, beta))"),
 }
 
 

@@ -339,3 +339,83 @@ def test_two_tone_golden_samples(orc):
         w = W[int(fi), int(t)]
         assert abs(w.real - re) <= 1e-13 * max(1.0, abs(re))
         assert abs(w.imag - im) <= 1e-13 * max(1.0, abs(im))
+
+
+# ------------------------------------------------- generalized Morse wavelet --
+# The GMW equation of "Fourier transformed formula", read with the unit step
+# and alpha = 2 (e gamma / beta)^(beta / gamma).  Its moments are Gamma
+# functions, which fix alpha, both exponents and the step independently of the
+# oracle's own expression.
+
+GMW_PARAMS = [(17.5, 3.0), (3.0, 1.0), (8.0, 2.0), (5.0, 4.0)]
+
+
+def _mp_gmw_alpha(beta, gamma):
+    return 2 * (mp.e * gamma / beta) ** (beta / gamma)
+
+
+@pytest.mark.parametrize("beta,gamma", GMW_PARAMS)
+def test_gmw_peak_is_two_at_closed_form_location(orc, beta, gamma):
+    """Peak value 2 at u_p = (beta / gamma)^(1 / gamma), zero slope there."""
+    b, g = mp.mpf(beta), mp.mpf(gamma)
+    up = float((b / g) ** (1 / g))
+    assert abs(orc.gmw_peak(beta, gamma) - up) <= 1e-15 * up
+    v = orc.gmw_spectrum([up, up * (1 - 1e-3), up * (1 + 1e-3)], beta, gamma)
+    assert abs(v[0] - 2.0) < 1e-13
+    assert v[1] < 2.0 and v[2] < 2.0
+    h = 1e-5 * up
+    d = orc.gmw_spectrum([up + h, up - h], beta, gamma)
+    assert abs(d[0] - d[1]) / (2 * h) < 1e-6
+
+
+@pytest.mark.parametrize("beta,gamma", GMW_PARAMS)
+def test_gmw_moments_match_gamma_functions(orc, beta, gamma):
+    """int_0^inf Psi_hat du = alpha Gamma((beta+1)/gamma) / gamma and
+    int_0^inf Psi_hat^2 du = alpha^2 Gamma((2 beta+1)/gamma) / (gamma 2^((2 beta+1)/gamma)),
+    by 40-digit quadrature of the oracle's values against mpmath's Gamma."""
+    b, g = mp.mpf(beta), mp.mpf(gamma)
+    a = _mp_gmw_alpha(b, g)
+    up = float((b / g) ** (1 / g))
+    f = lambda u: mp.mpf(orc.gmw_spectrum([float(u)], beta, gamma)[0])
+    # the integrand is below exp(-800) beyond u^gamma = 800 (the tail is
+    # negligible; the FP64 product alpha u^beta exp(-u^gamma) would overflow
+    # long before infinity)
+    umax = 800 ** (1 / gamma)
+    pts = [0, up / 2, up, 2 * up, 4 * up, umax]
+    m1 = mp.quad(f, pts)
+    m2 = mp.quad(lambda u: f(u) ** 2, pts)
+    e1 = a * mp.gamma((b + 1) / g) / g
+    e2 = a ** 2 * mp.gamma((2 * b + 1) / g) / (g * 2 ** ((2 * b + 1) / g))
+    assert abs(float(m1 / e1) - 1) < 1e-12
+    assert abs(float(m2 / e2) - 1) < 1e-12
+
+
+def test_gmw_vanishes_at_nonpositive_frequencies(orc):
+    """The unit-step reading: the GMW is analytic (no negative frequencies)."""
+    v = orc.gmw_spectrum([-5.0, -1.0, -1e-9, 0.0])
+    assert np.all(v == 0.0)
+    H = orc.wavelet_spectrum(1000, 1000.0, 40.0, None, "gmw")
+    assert np.all(H[500:] == 0.0) and H[0] == 0.0 and H.max() > 0
+    # near Nyquist: the Nyquist bin of an even length is a negative frequency
+    # (numpy's fftfreq convention), so it stays zero although the band reaches it
+    H = orc.wavelet_spectrum(1000, 1000.0, 450.0, None, "gmw")
+    assert H[499] > 0.1 * H.max() and np.all(H[500:] == 0.0)
+
+
+@pytest.mark.parametrize("beta,gamma", [(17.5, 3.0), (3.0, 1.0)])
+def test_gmw_tone_closed_form(orc, beta, gamma):
+    """A tone A sin(w0 t) at an exact bin b0: the analytic wavelet keeps only the
+    positive-frequency term, so at f0 = b0 sfreq / N the transform is exactly
+    W[t] = -i A sqrt(u_p sfreq / f0) exp(i w0 t) (peak value 2, s w0 = u_p)."""
+    N, sfreq, b0, A = 1000, 1000.0, 40, 0.7
+    f0 = b0 * sfreq / N
+    x = A * np.sin(2 * np.pi * b0 * np.arange(N) / N)
+    W = orc.cwt(x[None, :], sfreq, [f0, 2 * f0], None, kind="gmw", beta=beta, gamma=gamma)[0]
+    up = (mp.mpf(beta) / gamma) ** (1 / mp.mpf(gamma))
+    amp = float(A * mp.sqrt(up * sfreq / f0))
+    ref = -1j * amp * np.exp(2j * np.pi * b0 * np.arange(N) / N)
+    assert np.max(np.abs(W[0] - ref)) <= 1e-12 * amp
+    # at 2 f0 the tone sits at half the scaled peak frequency: Psi_hat(u_p / 2)
+    half = float(_mp_gmw_alpha(mp.mpf(beta), gamma) * (up / 2) ** beta * mp.exp(-(up / 2) ** gamma))
+    amp2 = float(A / 2 * mp.sqrt(up * sfreq / (2 * f0))) * half
+    assert np.max(np.abs(np.abs(W[1]) - amp2)) <= 1e-12 * amp
