@@ -46,7 +46,10 @@ extern "C" {
 #define CWT_E_AGAIN (-6)       /* nothing ready / queue full; retry later      */
 
 /* ---- plan options ---------------------------------------------------- */
-enum cwt_wavelet { CWT_WAVELET_MORLET = 0, CWT_WAVELET_GABOR = 1 };
+/* Morlet and Gabor: section "Fourier transformed formula"; GMW: the generalized
+ * Morse wavelet equation of the same section, read with the unit step U(omega)
+ * for sign(omega) and alpha = 2 (e gamma / beta)^(beta / gamma) (peak value 2). */
+enum cwt_wavelet { CWT_WAVELET_MORLET = 0, CWT_WAVELET_GABOR = 1, CWT_WAVELET_GMW = 2 };
 enum cwt_pad { CWT_PAD_SMOOTH7 = 0, CWT_PAD_POW2 = 1, CWT_PAD_NONE = 2, CWT_PAD_EXPLICIT = 3 };
 enum cwt_out { CWT_OUT_COMPLEX64 = 0, CWT_OUT_POWER_F32 = 1, CWT_OUT_BANDPOWER_F32 = 2 };
 enum cwt_precision {
@@ -72,9 +75,12 @@ typedef struct cwt_plan_opts {
                                  lo_k <= f < hi_k, or f == hi_k for the last band.
                                  Defaults: delta 1-4, theta 4-8, alpha 8-13,
                                  beta 13-30, gamma 30-100 Hz.  Copied at create. */
+    double gmw_beta;          /* GMW beta (default 17.5, the paper's value)        */
+    double gmw_gamma;         /* GMW gamma (default 3)                             */
 } cwt_plan_opts;
 
-/* Fill *opts with the defaults: Morlet, SMOOTH7, complex64, FP32, default bands. */
+/* Fill *opts with the defaults: Morlet, SMOOTH7, complex64, FP32, default bands,
+ * GMW beta = 17.5 and gamma = 3. */
 int cwt_plan_opts_init(cwt_plan_opts *opts);
 
 typedef struct cwt_plan cwt_plan;
@@ -83,11 +89,15 @@ typedef struct cwt_plan cwt_plan;
  * Create an immutable plan for signals of n samples at sfreq Hz, analysed at
  * n_freqs frequencies freqs[] (Hz).  The wavelet parameter sigma (the paper's
  * Morlet sigma, equal to the number of cycles and to omega0) is n_cycles[i]
- * per frequency, or omega0 for every frequency when n_cycles is NULL.
+ * per frequency, or omega0 for every frequency when n_cycles is NULL.  For
+ * the GMW, n_cycles and omega0 are not used (n_cycles may be NULL); the
+ * scale of frequency f is s = u_p / (2 pi f) with u_p = (beta/gamma)^(1/gamma)
+ * the wavelet's peak, from opts->gmw_beta and opts->gmw_gamma.
  *
  * Validation (CWT_E_INVALID): out != NULL; n >= 1; sfreq finite and > 0;
  * 1 <= n_freqs <= CWT_MAX_FREQS; every frequency finite with
- * 0 < f < sfreq / 2; every sigma finite and > 0; known enum values; for
+ * 0 < f < sfreq / 2; every sigma finite and > 0 (Morlet, Gabor), or
+ * gmw_beta and gmw_gamma finite and > 0 (GMW); known enum values; for
  * CWT_PAD_EXPLICIT explicit_len >= n; for band output every band has
  * lo < hi and owns at least one frequency, and n_bands <= CWT_MAX_BANDS.
  * A padded length above CWT_MAX_LEN, or whose prime factors are not all in

@@ -32,10 +32,13 @@ def _dptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _make_opts(lib, wavelet, pad, explicit_len, out, precision, bands):
+def _make_opts(lib, wavelet, pad, explicit_len, out, precision, bands, gmw_beta=17.5,
+               gmw_gamma=3.0):
     opts = _lib.PlanOpts()
     lib.cwt_plan_opts_init(ctypes.byref(opts))
     opts.wavelet = _lib.WAVELET[wavelet]
+    opts.gmw_beta = float(gmw_beta)
+    opts.gmw_gamma = float(gmw_gamma)
     opts.pad = _lib.PAD[pad]
     opts.explicit_len = int(explicit_len)
     opts.out = _lib.OUT[out]
@@ -48,7 +51,9 @@ def _make_opts(lib, wavelet, pad, explicit_len, out, precision, bands):
     return opts, edges
 
 
-def _cycles(freqs, n_cycles, omega0):
+def _cycles(freqs, n_cycles, omega0, wavelet="morlet"):
+    if wavelet == "gmw" and n_cycles is None and omega0 is None:
+        return None, None, 0.0  # not used by the GMW
     if n_cycles is not None:
         cyc = np.asarray(n_cycles, dtype=np.float64)
         if cyc.ndim == 0:
@@ -61,12 +66,14 @@ def _cycles(freqs, n_cycles, omega0):
 
 
 def describe(n, sfreq, freqs, n_cycles=None, omega0=None, wavelet="morlet", pad="smooth7",
-             explicit_len=0, out="complex64", precision="fp32", bands=None):
+             explicit_len=0, out="complex64", precision="fp32", bands=None, gmw_beta=17.5,
+             gmw_gamma=3.0):
     """Validate a plan request and describe it without a GPU (cwt_plan_describe)."""
     lib = _lib.load()
     freqs = np.ascontiguousarray(np.asarray(freqs, dtype=np.float64).ravel())
-    opts, edges = _make_opts(lib, wavelet, pad, explicit_len, out, precision, bands)
-    cyc, cyc_ptr, om = _cycles(freqs, n_cycles, omega0)
+    opts, edges = _make_opts(lib, wavelet, pad, explicit_len, out, precision, bands, gmw_beta,
+                             gmw_gamma)
+    cyc, cyc_ptr, om = _cycles(freqs, n_cycles, omega0, wavelet)
     desc = _lib.PlanDesc()
     _lib.check(lib.cwt_plan_describe(ctypes.byref(desc), int(n), float(sfreq),
                                      freqs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -78,17 +85,20 @@ class Plan:
     """A CWT plan: padded length, radix schedule and device-resident tables.
 
     n_cycles: one sigma per frequency (the paper's Morlet sigma), or None to
-    use omega0 for every frequency.  out: "complex64", "power" or "bandpower".
+    use omega0 for every frequency.  wavelet: "morlet", "gabor" or "gmw" (the
+    generalized Morse wavelet, gmw_beta / gmw_gamma; n_cycles not used).
+    out: "complex64", "power" or "bandpower".
     """
 
     def __init__(self, n, sfreq, freqs, n_cycles=None, omega0=None, wavelet="morlet",
                  pad="smooth7", explicit_len=0, out="complex64", precision="fp32", bands=None,
-                 stream=None):
+                 stream=None, gmw_beta=17.5, gmw_gamma=3.0):
         lib = _lib.load()
         self._lib = lib
         self.freqs = np.ascontiguousarray(np.asarray(freqs, dtype=np.float64).ravel())
-        opts, self._edges = _make_opts(lib, wavelet, pad, explicit_len, out, precision, bands)
-        self._cyc, cyc_ptr, om = _cycles(self.freqs, n_cycles, omega0)
+        opts, self._edges = _make_opts(lib, wavelet, pad, explicit_len, out, precision, bands,
+                                       gmw_beta, gmw_gamma)
+        self._cyc, cyc_ptr, om = _cycles(self.freqs, n_cycles, omega0, wavelet)
         handle = ctypes.c_void_p()
         self._ptr = None
         _lib.check(lib.cwt_plan_create(

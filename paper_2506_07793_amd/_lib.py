@@ -24,7 +24,7 @@ ERROR_NAMES = {
     CWT_E_AGAIN: "CWT_E_AGAIN",
 }
 
-WAVELET = {"morlet": 0, "gabor": 1}
+WAVELET = {"morlet": 0, "gabor": 1, "gmw": 2}
 PAD = {"smooth7": 0, "pow2": 1, "none": 2, "explicit": 3}
 OUT = {"complex64": 0, "power": 1, "bandpower": 2}
 PRECISION = {"fp32": 0, "split_f16": 1, "split_bf16": 2}
@@ -41,6 +41,8 @@ class PlanOpts(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("n_bands", ctypes.c_int32),
         ("band_edges", ctypes.POINTER(ctypes.c_double)),
+        ("gmw_beta", ctypes.c_double),
+        ("gmw_gamma", ctypes.c_double),
     ]
 
 

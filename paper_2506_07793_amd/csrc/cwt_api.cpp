@@ -153,12 +153,41 @@ bool make_radix_plan(int L, RadixPlan &rp)
 
 // Stored band of one frequency's spectrum: every signed bin whose value can
 // reach 1e-12 of the spectrum's main Gaussian (and, for Morlet, of the
-// kappa-weighted Gaussian at zero frequency).
-BandDesc spectrum_band(int L, double sfreq, double f, double sigma, int wavelet)
+// kappa-weighted Gaussian at zero frequency), or of the GMW's peak.  For the
+// GMW, sigma is the peak argument u_p, so s = sigma / (2 pi f) as for Morlet.
+// GMW: the u > 0 where (u/u_p)^beta exp(u_p^gamma - u^gamma) = eps, one on
+// each side of the peak u_p (the log ratio is concave with maximum 0 there),
+// by bisection.
+static void gmw_band(double beta, double gamma, double eps, double *ulo, double *uhi)
+{
+    const double up = std::pow(beta / gamma, 1.0 / gamma);
+    const double target = std::log(eps);
+    auto g = [&](double u) { return beta * std::log(u / up) - (std::pow(u, gamma) - std::pow(up, gamma)); };
+    double a = up, b = up;
+    while (g(a) > target && a > 1e-300) a *= 0.5;
+    double lo = a, hi = up;
+    for (int i = 0; i < 200; ++i) {
+        const double m = 0.5 * (lo + hi);
+        (g(m) > target ? hi : lo) = m;
+    }
+    *ulo = lo;
+    while (g(b) > target) b *= 2.0;
+    lo = up;
+    hi = b;
+    for (int i = 0; i < 200; ++i) {
+        const double m = 0.5 * (lo + hi);
+        (g(m) > target ? lo : hi) = m;
+    }
+    *uhi = hi;
+}
+
+BandDesc spectrum_band(int L, double sfreq, double f, double sigma, int wavelet, double beta,
+                       double gamma)
 {
     const double eps = 1e-12;
     const double xm = std::sqrt(2.0 * std::log(1.0 / eps));
     double ulo = sigma - xm, uhi = sigma + xm;
+    if (wavelet == CWT_WAVELET_GMW) gmw_band(beta, gamma, eps, &ulo, &uhi);
     if (wavelet == CWT_WAVELET_MORLET) {
         const double kappa = std::exp(-0.5 * sigma * sigma);
         if (kappa > eps) {
@@ -198,6 +227,8 @@ extern "C" int cwt_plan_opts_init(cwt_plan_opts *o)
     if (!o) return fail(CWT_E_INVALID, "cwt_plan_opts_init: opts is NULL");
     std::memset(o, 0, sizeof *o);
     o->wavelet = CWT_WAVELET_MORLET;
+    o->gmw_beta = 17.5;
+    o->gmw_gamma = 3.0;
     o->pad = CWT_PAD_SMOOTH7;
     o->out = CWT_OUT_COMPLEX64;
     o->precision = CWT_PREC_FP32;
@@ -223,8 +254,14 @@ int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
     if (n_freqs < 1 || n_freqs > CWT_MAX_FREQS)
         return fail(CWT_E_INVALID, "n_freqs must be in [1, %d] (got %d)", CWT_MAX_FREQS, n_freqs);
     if (!freqs) return fail(CWT_E_INVALID, "freqs is NULL");
-    if (o.wavelet != CWT_WAVELET_MORLET && o.wavelet != CWT_WAVELET_GABOR)
+    if (o.wavelet != CWT_WAVELET_MORLET && o.wavelet != CWT_WAVELET_GABOR &&
+        o.wavelet != CWT_WAVELET_GMW)
         return fail(CWT_E_INVALID, "unknown wavelet %d", o.wavelet);
+    const bool gmw = o.wavelet == CWT_WAVELET_GMW;
+    if (gmw && (!std::isfinite(o.gmw_beta) || o.gmw_beta <= 0 || !std::isfinite(o.gmw_gamma) ||
+                o.gmw_gamma <= 0))
+        return fail(CWT_E_INVALID, "GMW beta and gamma must be finite and > 0 (got %g, %g)",
+                    o.gmw_beta, o.gmw_gamma);
     if (o.pad < CWT_PAD_SMOOTH7 || o.pad > CWT_PAD_EXPLICIT)
         return fail(CWT_E_INVALID, "unknown pad mode %d", o.pad);
     if (o.out < CWT_OUT_COMPLEX64 || o.out > CWT_OUT_BANDPOWER_F32)
@@ -241,6 +278,10 @@ int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
         if (!std::isfinite(f) || f <= 0 || f >= 0.5 * sfreq)
             return fail(CWT_E_INVALID, "freqs[%d] = %g outside (0, sfreq/2 = %g)", i, f,
                         0.5 * sfreq);
+        if (gmw) {
+            P.sigmas[i] = std::pow(o.gmw_beta / o.gmw_gamma, 1.0 / o.gmw_gamma);
+            continue;
+        }
         const double s = n_cycles ? n_cycles[i] : omega0;
         if (!std::isfinite(s) || s <= 0)
             return fail(CWT_E_INVALID, "n_cycles/omega0 for freqs[%d] must be finite and > 0", i);
@@ -302,7 +343,8 @@ int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
     P.bands.resize(n_freqs);
     int off = 0, maxK = 0;
     for (int i = 0; i < n_freqs; ++i) {
-        BandDesc bd = spectrum_band(P.L, sfreq, freqs[i], P.sigmas[i], o.wavelet);
+        BandDesc bd = spectrum_band(P.L, sfreq, freqs[i], P.sigmas[i], o.wavelet, o.gmw_beta,
+                                    o.gmw_gamma);
         bd.off = off;
         off += bd.K;
         maxK = std::max(maxK, bd.K);
@@ -386,6 +428,8 @@ int upload_plan(cwt_plan &P, hipStream_t s)
     g.L = P.L;
     g.F = P.F;
     g.wavelet = P.opts.wavelet;
+    g.gmw_beta = P.opts.gmw_beta;
+    g.gmw_gamma = P.opts.gmw_gamma;
     g.freqs = P.d_freqs;
     g.sigmas = P.d_sigmas;
     g.band = P.d_band;

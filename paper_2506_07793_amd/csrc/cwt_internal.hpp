@@ -53,7 +53,8 @@ int64_t pad_length(int64_t n, int mode, int64_t explicit_len);
 bool make_radix_plan(int L, cwtk::RadixPlan &rp);
 void radix_candidates(int L, std::vector<cwtk::RadixPlan> &out);
 void apply_tuning_cache(cwt_plan &P);
-cwtk::BandDesc spectrum_band(int L, double sfreq, double f, double sigma, int wavelet);
+cwtk::BandDesc spectrum_band(int L, double sfreq, double f, double sigma, int wavelet,
+                             double gmw_beta, double gmw_gamma);
 int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
                       int32_t n_freqs, const double *n_cycles, double omega0,
                       const cwt_plan_opts *opts);

@@ -1,8 +1,8 @@
 // HIP kernels of the plain FP32 CWT path for gfx950.
 //
-//   k_generate : FP64 wavelet spectra (Morlet / Gabor Fourier-domain
-//                equations, evaluated at s * omega_b) and the FP64 twiddle
-//                table, each rounded once to FP32.
+//   k_generate : FP64 wavelet spectra (Morlet / Gabor / generalized Morse
+//                Fourier-domain equations, evaluated at s * omega_b) and the
+//                FP64 twiddle table, each rounded once to FP32.
 //   k_forward  : forward real FFT of two channels per workgroup (packed as
 //                one complex transform), half spectra to the workspace.
 //   k_main     : per (channel, frequency) or (channel, band): spectral
@@ -33,8 +33,17 @@ __global__ void k_generate(GenParams p)
         }
         const int bt = bd.lo + k;  // signed bin
         const double u = s * (2.0 * PI * p.sfreq * (double)bt / (double)p.L);
-        const double du = sigma - u;
-        const double psi = c * pow(PI, -0.25) * (exp(-0.5 * du * du) - kappa * exp(-0.5 * u * u));
+        double psi;
+        if (p.wavelet == 2) {
+            // generalized Morse: alpha u^beta exp(-u^gamma) for u > 0, zero
+            // otherwise; alpha = 2 (e gamma / beta)^(beta / gamma), in logs
+            const double be = p.gmw_beta, ga = p.gmw_gamma;
+            const double log_alpha = log(2.0) + (be / ga) * (1.0 + log(ga / be));
+            psi = (u > 0.0) ? exp(log_alpha + be * log(u) - pow(u, ga)) : 0.0;
+        } else {
+            const double du = sigma - u;
+            psi = c * pow(PI, -0.25) * (exp(-0.5 * du * du) - kappa * exp(-0.5 * u * u));
+        }
         const double h = sqrt(2.0 * PI * s * p.sfreq) * psi / (double)p.L;
         p.H[bd.off + k] = (float)h;
     } else {

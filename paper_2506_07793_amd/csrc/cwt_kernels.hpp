@@ -114,7 +114,8 @@ struct GenParams {
     double sfreq;
     int L;
     int F;
-    int wavelet;           // 0 Morlet, 1 Gabor
+    int wavelet;           // 0 Morlet, 1 Gabor, 2 generalized Morse
+    double gmw_beta, gmw_gamma;
     const double *freqs;   // [F] device
     const double *sigmas;  // [F] device
     const BandDesc *band;  // [F] device

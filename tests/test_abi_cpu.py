@@ -122,9 +122,12 @@ def test_validation_raw_abi():
                                  None) == _lib.CWT_E_INVALID
     opts = _lib.PlanOpts()
     lib.cwt_plan_opts_init(ctypes.byref(opts))
-    for field, bad in (("wavelet", 7), ("pad", 9), ("out", 5), ("precision", 11)):
+    for field, bad in (("wavelet", 7), ("pad", 9), ("out", 5), ("precision", 11),
+                       ("gmw_beta", -1.0), ("gmw_gamma", 0.0)):
         o = _lib.PlanOpts()
         lib.cwt_plan_opts_init(ctypes.byref(o))
+        if field.startswith("gmw_"):
+            o.wavelet = _lib.WAVELET["gmw"]
         setattr(o, field, bad)
         rc = lib.cwt_plan_describe(ctypes.byref(d), 100, 1000.0, fp, 1, None, 7.0, ctypes.byref(o))
         assert rc == _lib.CWT_E_INVALID, field
@@ -169,6 +172,22 @@ def test_spectrum_band_covers_threshold():
         need += int(np.sum(H >= 1e-12 * H.max()))
     assert d.spectrum_bins >= need
     assert d.spectrum_bins <= 2 * need  # the band is not wastefully wide
+
+
+@pytest.mark.parametrize("beta,gamma", [(17.5, 3.0), (3.0, 1.0)])
+def test_gmw_band_covers_threshold_per_frequency(beta, gamma):
+    """GMW plans: for every frequency the stored bins cover each bin whose
+    oracle value reaches 1e-12 of the peak, with little excess; n_cycles is
+    not needed."""
+    import oracle
+    L, sfreq = 4096, 1000.0
+    for f in synth.log_freqs(0.5, 450.0, 25):
+        d = cwt.describe(L, sfreq, [f], wavelet="gmw", gmw_beta=beta, gmw_gamma=gamma)
+        H = np.abs(oracle.wavelet_spectrum(L, sfreq, f, None, "gmw", beta, gamma))
+        need = np.nonzero(H >= 1e-12 * H.max())[0]
+        span = need.max() - need.min() + 1  # positive bins only: one contiguous run
+        assert d.max_band_bins >= span, (f, d.max_band_bins, span)
+        assert d.max_band_bins <= span + 4, (f, d.max_band_bins, span)
 
 
 def test_stream_validation_without_gpu():

@@ -42,16 +42,18 @@ def _parity(Wg, Wr, label):
 # ------------------------------------------------------------------ tables --
 
 @pytest.mark.parametrize("n,sfreq,F,wavelet", [(4096, 1000.0, 100, "morlet"), (1000, 1000.0, 50, "morlet"),
-                                              (2000, 1000.0, 40, "gabor"), (4116, 2048.0, 30, "morlet")])
+                                              (2000, 1000.0, 40, "gabor"), (4116, 2048.0, 30, "morlet"),
+                                              (4096, 1000.0, 60, "gmw"), (1000, 1000.0, 40, "gmw")])
 def test_tables_within_one_ulp_of_fp64(n, sfreq, F, wavelet):
     """FP64 GPU generators: each stored spectrum bin (1/L folded in) and each
     twiddle is within one FP32 ulp of the FP64 value."""
-    freqs = synth.log_freqs(1.0, min(100.0, 0.45 * sfreq), F)
+    gmw = wavelet == "gmw"
+    freqs = synth.log_freqs(1.0, (0.45 if gmw else min(100.0 / sfreq, 0.45)) * sfreq, F)
     cyc = synth.eeg_cycles(freqs)
-    plan = cwt.Plan(n, sfreq, freqs, n_cycles=cyc, wavelet=wavelet)
+    plan = cwt.Plan(n, sfreq, freqs, n_cycles=None if gmw else cyc, wavelet=wavelet)
     H, band, tw = plan.tables()
     L = plan.L
-    kind = oracle.GABOR if wavelet == "gabor" else oracle.MORLET
+    kind = {"gabor": oracle.GABOR, "gmw": oracle.GMW}.get(wavelet, oracle.MORLET)
     for i, (f, s) in enumerate(zip(freqs, cyc)):
         lo, K, off = band[i]
         Hf = oracle.wavelet_spectrum(L, sfreq, f, s, kind) / L
@@ -422,4 +424,48 @@ def test_execute_batches_matches_execute(n, precision, out):
                                    ws.numel() // 2, None) == _lib.CWT_E_INVALID  # one half only
     assert lib.cwt_execute_batches(plan.handle, vp(x.data_ptr()), -1, 2, C, vp(outb.data_ptr()),
                                    0, vp(ws.data_ptr()), ws.numel(), None) == _lib.CWT_E_INVALID
+    plan.close()
+
+
+
+# ------------------------------------------------ generalized Morse wavelet --
+
+@pytest.mark.parametrize("n,pad,out", [(4096, "smooth7", "complex64"), (4096, "smooth7", "power"),
+                                       (4096, "smooth7", "bandpower"), (1000, "smooth7", "complex64"),
+                                       (3000, "pow2", "complex64"), (777, "smooth7", "power")])
+def test_gmw_parity(n, pad, out):
+    """GMW plans (beta 17.5, gamma 3, the paper's values) against the oracle:
+    register-resident (band and wide rows), runtime-radix and power-of-two
+    lengths, every output mode."""
+    d = synth.eeg_64ch(C=2, N=n, F=40)
+    x, sfreq, freqs = d["x"], d["sfreq"], d["freqs"]
+    plan, W = _run(x, sfreq, freqs, None, wavelet="gmw", pad=pad, out=out)
+    ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, None, kind="gmw", L=plan.L)
+    if out == "complex64":
+        _parity(W, ref, "gmw n=%d L=%d kernel=%d" % (n, plan.L, plan.desc.kernel))
+    else:
+        Pr = oracle.power(ref)
+        if out == "bandpower":
+            Pr = oracle.band_power(Pr, oracle.band_groups(freqs))
+        e = np.max(np.abs(W - Pr)) / Pr.max()
+        print("gmw %s n=%d e=%.3e" % (out, n, e))
+        assert e <= TOL_P
+    plan.close()
+
+
+@pytest.mark.parametrize("beta,gamma", [(17.5, 3.0), (3.0, 1.0), (8.0, 2.0)])
+def test_gmw_tone_amplitude(beta, gamma):
+    """A tone A sin(w0 t) at an exact bin: at f0 the GMW transform is
+    -i A sqrt(u_p sfreq / f0) exp(i w0 t) (closed form; the oracle's own pin)."""
+    N, sfreq, b0, A = 4096, 1000.0, 164, 20.0
+    f0 = b0 * sfreq / N
+    x = (A * np.sin(2 * np.pi * b0 * np.arange(N) / N)).astype(np.float32)
+    plan = cwt.Plan(N, sfreq, [f0], wavelet="gmw", gmw_beta=beta, gmw_gamma=gamma)
+    W = plan.execute(torch.from_numpy(x[None, :]).cuda()).cpu().numpy()[0, 0]
+    up = (beta / gamma) ** (1.0 / gamma)
+    amp = A * np.sqrt(up * sfreq / f0)
+    ref = -1j * amp * np.exp(2j * np.pi * b0 * np.arange(N) / N)
+    e = np.max(np.abs(W - ref)) / amp
+    print("gmw tone beta=%g gamma=%g e=%.3e" % (beta, gamma, e))
+    assert e <= 1e-5
     plan.close()
