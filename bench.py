@@ -87,6 +87,8 @@ def parse():
                     help="timed steps of the 256-recording batch run (0 skips it)")
     ap.add_argument("--stream-seconds", type=float, default=6.0,
                     help="real-time length of each streaming run (0 skips the streaming runs)")
+    ap.add_argument("--length-sweep", type=int, default=1,
+                    help="1: run the N = 100..2500 length sweep (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (scales the HBM "
                          "byte counters of a profiler run)")
@@ -173,6 +175,81 @@ def bench_batch(steps, n_rec=256):
     for p in plans:
         p.close()
     torch.cuda.empty_cache()
+    return res
+
+
+def bench_length_sweep(reps=100):
+    """Length sweep (section "Wavelength and flexibility", Figure 4): signals of
+    N = 100 ... 2500 samples at 1000 Hz (every 100, the largest prime at or
+    below each, and the powers of two in range), Morlet sigma 7 at 30-90 Hz in
+    1 Hz steps (61 frequencies), complex64 out.  Each length: `reps` calls of
+    cwt_execute (forward + transform) on 1 channel and on 64 channels, timed
+    with events; plus the plan-creation time of the paper's Table 2 case
+    (61 wavelets of 1 s at 1000 Hz).  Reports the times, a least-squares line
+    through (N, time) and, for each prime, its time over the mean of the two
+    nearest multiples of 100."""
+    import numpy as np
+    import torch
+
+    import paper_2506_07793_amd as cwt
+    import synth
+
+    def is_prime(m):
+        return m > 1 and all(m % d for d in range(2, int(m ** 0.5) + 1))
+
+    rounds = list(range(100, 2501, 100))
+    primes = sorted({max(p for p in range(2, n + 1) if is_prime(p)) for n in rounds})
+    pows = [128, 256, 512, 1024, 2048]
+    lengths = sorted(set(rounds) | set(primes) | set(pows))
+    sfreq, freqs = 1000.0, np.arange(30.0, 91.0)
+    stream = torch.cuda.Stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    x64 = torch.from_numpy(synth.eeg(64, 2500, sfreq, 7)).cuda()
+    rows = []
+    t_create = []
+    for N in lengths:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = cwt.Plan(N, sfreq, freqs, n_cycles=7.0, stream=stream)
+        stream.synchronize()
+        t_create.append((N, (time.perf_counter() - t0) * 1e3))
+        rec = {"N": N, "L": plan.L, "radices": plan.radices, "kernel": int(plan.desc.kernel),
+               "kind": "prime" if is_prime(N) else ("pow2" if N in pows else "round")}
+        for C in (1, 64):
+            x = x64[:C, :N].contiguous()
+            out = plan.alloc_output(C)
+            ws = plan.alloc_workspace(C)
+            with torch.cuda.stream(stream):
+                for _ in range(5):
+                    plan.execute(x, out=out, ws=ws, stream=stream)
+                ev0.record(stream)
+                for _ in range(reps):
+                    plan.execute(x, out=out, ws=ws, stream=stream)
+                ev1.record(stream)
+                torch.cuda.synchronize()
+            rec["ms_C%d" % C] = ev0.elapsed_time(ev1) / reps
+        rows.append(rec)
+        plan.close()
+    res = {"workload": "N = 100..2500 at 1000 Hz, Morlet sigma 7, 61 freqs 30-90 Hz, complex64, "
+                       "%d calls per length" % reps, "lengths": rows}
+    for C in (1, 64):
+        n = np.array([r["N"] for r in rows], float)
+        t = np.array([r["ms_C%d" % C] for r in rows])
+        a, b = np.polyfit(n, t, 1)
+        pred = a * n + b
+        r2 = 1 - np.sum((t - pred) ** 2) / np.sum((t - t.mean()) ** 2)
+        by_n = {r["N"]: r["ms_C%d" % C] for r in rows}
+        ratios = []
+        for r in rows:
+            if r["kind"] == "prime":
+                lo, hi = (r["N"] // 100) * 100, (r["N"] // 100 + 1) * 100
+                ref = [by_n[m] for m in (lo, hi) if m in by_n]
+                if ref:
+                    ratios.append(r["ms_C%d" % C] / np.mean(ref))
+        res["C%d" % C] = {"ms_per_sample_slope": a, "ms_intercept": b, "r2_linear": r2,
+                          "prime_over_neighbours_max": float(np.max(ratios)),
+                          "prime_over_neighbours_mean": float(np.mean(ratios))}
+    res["plan_create_ms_N1000_61_wavelets"] = dict(t_create)[1000]
     return res
 
 
@@ -472,6 +549,9 @@ def main():
 
     if args.batch_steps > 0:
         result["batch"] = bench_batch(args.batch_steps)
+
+    if args.length_sweep:
+        result["length_sweep"] = bench_length_sweep()
 
     if args.stream_seconds > 0:
         result["stream"] = [

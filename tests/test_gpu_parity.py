@@ -469,3 +469,15 @@ def test_gmw_tone_amplitude(beta, gamma):
     print("gmw tone beta=%g gamma=%g e=%.3e" % (beta, gamma, e))
     assert e <= 1e-5
     plan.close()
+
+
+@pytest.mark.parametrize("N", [101, 127, 128, 499, 997, 1024, 1999, 2048, 2477, 2500])
+def test_length_sweep_lengths(N):
+    """Lengths of the length sweep (primes, powers of two, round numbers;
+    Morlet sigma 7, 61 frequencies 30-90 Hz at 1000 Hz) against the oracle."""
+    sfreq, freqs = 1000.0, np.arange(30.0, 91.0)
+    x = synth.eeg(2, N, sfreq, N)
+    plan, W = _run(x, sfreq, freqs, 7.0)
+    ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, 7.0, L=plan.L)
+    _parity(W, ref, "sweep N=%d L=%d kernel=%d" % (N, plan.L, plan.desc.kernel))
+    plan.close()
