@@ -50,7 +50,21 @@ extern "C" {
  * Morse wavelet equation of the same section, read with the unit step U(omega)
  * for sign(omega) and alpha = 2 (e gamma / beta)^(beta / gamma) (peak value 2). */
 enum cwt_wavelet { CWT_WAVELET_MORLET = 0, CWT_WAVELET_GABOR = 1, CWT_WAVELET_GMW = 2 };
-enum cwt_pad { CWT_PAD_SMOOTH7 = 0, CWT_PAD_POW2 = 1, CWT_PAD_NONE = 2, CWT_PAD_EXPLICIT = 3 };
+/* CWT_PAD_LINEAR: the smallest 7-smooth L >= n + S, S = ceil(sqrt(2 ln 1e12)
+ * s_max sfreq) + 1 the one-sided time support of the widest wavelet (the
+ * Morlet / Gabor Gaussian envelope falls below 1e-12 of its peak beyond it;
+ * s_max = max sigma / (2 pi f)).  The cyclic wrap then never reaches an output
+ * sample, and the result equals the linear convolution of the zero-extended
+ * signal with the wavelet (no edge wrap-around; section "Fourier transformed
+ * formula" notes the cyclic result differs near the edges).  Morlet and
+ * Gabor only (the GMW gives CWT_E_UNSUPPORTED). */
+enum cwt_pad {
+    CWT_PAD_SMOOTH7 = 0,
+    CWT_PAD_POW2 = 1,
+    CWT_PAD_NONE = 2,
+    CWT_PAD_EXPLICIT = 3,
+    CWT_PAD_LINEAR = 4
+};
 enum cwt_out { CWT_OUT_COMPLEX64 = 0, CWT_OUT_POWER_F32 = 1, CWT_OUT_BANDPOWER_F32 = 2 };
 enum cwt_precision {
     CWT_PREC_FP32 = 0,       /* FP32 radix-2/3/4/5/7/8/16 FFT in LDS               */

@@ -109,9 +109,24 @@ def num_threads():
     return int(_load().orc_num_threads())
 
 
-def pad_length(n, mode="smooth7", explicit=None):
-    """Padded FFT length for a signal of n samples ("Fast Fourier transform")."""
+def linear_support(sfreq, freqs, n_cycles):
+    """One-sided time support, in samples, of the widest Morlet / Gabor
+    wavelet of a grid: its Gaussian envelope exp(-u^2/2), u = t / s, is below
+    1e-12 of the peak for u > sqrt(2 ln 1e12); s = sigma / (2 pi f)."""
+    freqs = np.asarray(freqs, dtype=np.float64)
+    s = sigmas_for(freqs, n_cycles) / (2 * np.pi * freqs)
+    return int(np.ceil(np.sqrt(2 * np.log(1e12)) * s.max() * sfreq)) + 1
+
+
+def pad_length(n, mode="smooth7", explicit=None, support=None):
+    """Padded FFT length for a signal of n samples ("Fast Fourier transform");
+    "linear": the smooth length >= n + support (no cyclic wrap reaches the
+    output; ``support`` from linear_support)."""
     lib = _load()
+    if mode == "linear":
+        if support is None:
+            raise ValueError("linear padding needs the wavelet support")
+        return int(lib.orc_pad_smooth7(int(n) + int(support)))
     if mode == "smooth7":
         return int(lib.orc_pad_smooth7(int(n)))
     if mode == "pow2":
@@ -213,7 +228,8 @@ def cwt(x, sfreq, freqs, n_cycles, kind=MORLET, pad="smooth7", L=None, rows=None
     freqs = np.asarray(freqs, dtype=np.float64)
     F = freqs.shape[0]
     if L is None:
-        L = pad_length(N, pad)
+        sup = linear_support(sfreq, freqs, n_cycles) if pad == "linear" else None
+        L = pad_length(N, pad, support=sup)
     if L < N:
         raise ValueError("padded length shorter than the signal")
     if nt is None:

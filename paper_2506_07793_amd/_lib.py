@@ -25,7 +25,7 @@ ERROR_NAMES = {
 }
 
 WAVELET = {"morlet": 0, "gabor": 1, "gmw": 2}
-PAD = {"smooth7": 0, "pow2": 1, "none": 2, "explicit": 3}
+PAD = {"smooth7": 0, "pow2": 1, "none": 2, "explicit": 3, "linear": 4}
 OUT = {"complex64": 0, "power": 1, "bandpower": 2}
 PRECISION = {"fp32": 0, "split_f16": 1, "split_bf16": 2}
 

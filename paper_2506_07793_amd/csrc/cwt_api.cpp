@@ -262,7 +262,7 @@ int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
                 o.gmw_gamma <= 0))
         return fail(CWT_E_INVALID, "GMW beta and gamma must be finite and > 0 (got %g, %g)",
                     o.gmw_beta, o.gmw_gamma);
-    if (o.pad < CWT_PAD_SMOOTH7 || o.pad > CWT_PAD_EXPLICIT)
+    if (o.pad < CWT_PAD_SMOOTH7 || o.pad > CWT_PAD_LINEAR)
         return fail(CWT_E_INVALID, "unknown pad mode %d", o.pad);
     if (o.out < CWT_OUT_COMPLEX64 || o.out > CWT_OUT_BANDPOWER_F32)
         return fail(CWT_E_INVALID, "unknown output mode %d", o.out);
@@ -322,7 +322,26 @@ int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
     } else {
         P.n_bands = 0;
     }
-    const int64_t L = pad_length(n, o.pad, o.explicit_len);
+    int64_t L;
+    if (o.pad == CWT_PAD_LINEAR) {
+        if (gmw)
+            return fail(CWT_E_UNSUPPORTED,
+                        "linear edge mode needs the Gaussian time support of Morlet / Gabor");
+        // one-sided support of the widest wavelet: exp(-u^2/2) < 1e-12 beyond
+        // u = sqrt(2 ln 1e12), u = t / s
+        const double umax = std::sqrt(2.0 * std::log(1e12));
+        double smax = 0;
+        for (int i = 0; i < n_freqs; ++i)
+            smax = std::max(smax, P.sigmas[i] / (2.0 * 3.14159265358979323846 * freqs[i]));
+        const double S = std::ceil(umax * smax * sfreq) + 1.0;
+        if (!(n + S <= (double)CWT_MAX_LEN))
+            return fail(CWT_E_UNSUPPORTED,
+                        "linear edge mode needs L >= n + %.0f samples, above %d", S,
+                        CWT_MAX_LEN);
+        L = pad_length(n + (int64_t)S, CWT_PAD_SMOOTH7, 0);
+    } else {
+        L = pad_length(n, o.pad, o.explicit_len);
+    }
     if (L > CWT_MAX_LEN)
         return fail(CWT_E_UNSUPPORTED, "padded length %lld exceeds the LDS limit %d",
                     (long long)L, CWT_MAX_LEN);

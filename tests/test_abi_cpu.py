@@ -213,3 +213,22 @@ def test_stream_validation_without_gpu():
     t1 = lib.cwt_now_ns()
     t2 = lib.cwt_now_ns()
     assert t2 >= t1 > 0
+
+
+def test_linear_edge_mode_length():
+    """pad="linear": L is the smallest 7-smooth length >= n + the oracle's
+    support of the widest wavelet; GMW and too-long requests are unsupported."""
+    import oracle
+    freqs = synth.log_freqs(1.0, 100.0, 40)
+    cyc = synth.eeg_cycles(freqs)
+    for n, sfreq in ((2000, 1000.0), (777, 250.0), (4096, 2048.0)):
+        d = cwt.describe(n, sfreq, freqs[freqs < 0.45 * sfreq], n_cycles=cyc[freqs < 0.45 * sfreq],
+                         pad="linear")
+        S = oracle.linear_support(sfreq, freqs[freqs < 0.45 * sfreq], cyc[freqs < 0.45 * sfreq])
+        assert d.L == oracle.pad_length(n, "linear", support=S), (n, d.L, S)
+    with pytest.raises(cwt.CwtError) as e:
+        cwt.describe(2000, 1000.0, [10.0], wavelet="gmw", pad="linear")
+    assert e.value.code == _lib.CWT_E_UNSUPPORTED
+    with pytest.raises(cwt.CwtError) as e:
+        cwt.describe(20000, 1000.0, [0.5], n_cycles=[10.0], pad="linear")
+    assert e.value.code == _lib.CWT_E_UNSUPPORTED

@@ -481,3 +481,16 @@ def test_length_sweep_lengths(N):
     ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, 7.0, L=plan.L)
     _parity(W, ref, "sweep N=%d L=%d kernel=%d" % (N, plan.L, plan.desc.kernel))
     plan.close()
+
+
+@pytest.mark.parametrize("n,sfreq", [(2000, 1000.0), (1000, 250.0)])
+def test_linear_edge_mode_parity(n, sfreq):
+    """pad="linear" (no cyclic wrap at the edges) against the oracle."""
+    freqs = synth.log_freqs(1.0, min(100.0, 0.45 * sfreq), 30)
+    cyc = synth.eeg_cycles(freqs)
+    x = synth.eeg(2, n, sfreq, 21)
+    plan, W = _run(x, sfreq, freqs, cyc, pad="linear")
+    ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc, pad="linear")
+    assert plan.L == oracle.pad_length(n, "linear", support=oracle.linear_support(sfreq, freqs, cyc))
+    _parity(W, ref, "linear n=%d L=%d" % (n, plan.L))
+    plan.close()

@@ -419,3 +419,42 @@ def test_gmw_tone_closed_form(orc, beta, gamma):
     half = float(_mp_gmw_alpha(mp.mpf(beta), gamma) * (up / 2) ** beta * mp.exp(-(up / 2) ** gamma))
     amp2 = float(A / 2 * mp.sqrt(up * sfreq / (2 * f0))) * half
     assert np.max(np.abs(np.abs(W[1]) - amp2)) <= 1e-12 * amp
+
+
+# ------------------------------------------------------- linear edge mode --
+
+def _time_morlet(m, sfreq, f, sigma, kind=0):
+    """sqrt(dt) psi_s(m dt), the textbook time-domain Morlet (not periodised)."""
+    if kind == 0:
+        kappa = math.exp(-sigma * sigma / 2)
+        c = (1 + math.exp(-sigma * sigma) - 2 * math.exp(-0.75 * sigma * sigma)) ** -0.5
+    else:
+        kappa, c = 0.0, 1.0
+    s = sigma / (2 * math.pi * f)
+    dt = 1.0 / sfreq
+    u = np.asarray(m, dtype=np.float64) * dt / s
+    return math.sqrt(dt) * s ** -0.5 * c * math.pi ** -0.25 * np.exp(-0.5 * u * u) * (
+        np.exp(1j * sigma * u) - kappa)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_linear_mode_equals_direct_linear_convolution(orc, kind):
+    """With L >= n + support, the cyclic definition equals the linear
+    convolution of the zero-extended signal with the textbook wavelet: no
+    wrap-around at the edges (the cyclic result at L = n differs there)."""
+    rng = np.random.default_rng(11)
+    N, sfreq = 300, 1000.0
+    freqs = np.array([4.0, 20.0, 60.0])
+    cyc = np.array([3.0, 6.0, 10.0])
+    x = rng.normal(size=N)
+    S = orc.linear_support(sfreq, freqs, cyc)
+    L = orc.pad_length(N, "linear", support=S)
+    assert L >= N + S
+    W = orc.cwt(x[None, :], sfreq, freqs, cyc, kind=kind, pad="linear")[0]
+    Wc = orc.cwt(x[None, :], sfreq, freqs, cyc, kind=kind, pad="none")[0]
+    t = np.arange(N)
+    for fi, (f, sg) in enumerate(zip(freqs, cyc)):
+        ref = np.array([np.sum(x * _time_morlet(tt - t, sfreq, f, sg, kind)) for tt in t])
+        assert np.max(np.abs(W[fi] - ref)) <= 1e-11 * np.max(np.abs(ref))
+    # the 4 Hz wavelet is longer than the signal: the cyclic result wraps
+    assert np.max(np.abs(Wc[0] - W[0])) > 0.1 * np.max(np.abs(W[0]))
