@@ -263,6 +263,61 @@ def cwt(x, sfreq, freqs, n_cycles, kind=MORLET, pad="smooth7", L=None, rows=None
     return W
 
 
+def user_wavelet_time(wavelets, L):
+    """Place sampled time-domain wavelets on a length-L circle: sample j of a
+    wavelet of w samples sits at time (j - w // 2) / sfreq, i.e. at index
+    (j - w // 2) mod L.  [F, w] complex -> [F, L] complex128."""
+    wv = np.atleast_2d(np.asarray(wavelets, dtype=np.complex128))
+    F, w = wv.shape
+    if w > L:
+        raise ValueError("wavelet longer than the padded length")
+    h = np.zeros((F, L), dtype=np.complex128)
+    idx = (np.arange(w) - w // 2) % L
+    h[:, idx] = wv
+    return h
+
+
+def cwt_user(x, wavelets, pad="smooth7", L=None, rows=None, t0=0, nt=None):
+    """CWT with sampled time-domain wavelets (the two-FFT form of "Fourier
+    transformed formula": IFFT(FFT(x_pad) FFT(psi_pad)), i.e. the cyclic
+    convolution of the padded signal with each placed wavelet), computed
+    directly as that cyclic convolution.  "linear" padding uses the longest
+    one-sided extent of the wavelets as the support."""
+    x = np.asarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[None, :]
+    x = np.ascontiguousarray(x)
+    C, N = x.shape
+    wv = np.atleast_2d(np.asarray(wavelets, dtype=np.complex128))
+    F, w = wv.shape
+    if L is None:
+        sup = max(w // 2, w - 1 - w // 2) + 1 if pad == "linear" else None
+        L = pad_length(N, pad, support=sup)
+    if nt is None:
+        nt = N - t0
+    h = user_wavelet_time(wv, L)
+    h_re = np.ascontiguousarray(h.real)
+    h_im = np.ascontiguousarray(h.imag)
+    if rows is None:
+        rc, rf = np.meshgrid(np.arange(C), np.arange(F), indexing="ij")
+        rc, rf = rc.ravel(), rf.ravel()
+    else:
+        rows = np.asarray(rows, dtype=np.int64).reshape(-1, 2)
+        rc, rf = rows[:, 0], rows[:, 1]
+    rc = np.ascontiguousarray(rc, dtype=np.int64)
+    rf = np.ascontiguousarray(rf, dtype=np.int64)
+    n_rows = rc.shape[0]
+    w_re = np.empty((n_rows, nt))
+    w_im = np.empty((n_rows, nt))
+    _load().orc_cwt_rows(_ptr(x), C, N, L, _ptr(h_re), _ptr(h_im), F,
+                         _ptr(rc, ctypes.c_int64), _ptr(rf, ctypes.c_int64), n_rows, t0, nt,
+                         _ptr(w_re), _ptr(w_im))
+    W = w_re + 1j * w_im
+    if rows is None:
+        return W.reshape(C, F, nt)
+    return W
+
+
 def power(W):
     """|W|^2 (section "Precision" compares power values)."""
     return W.real ** 2 + W.imag ** 2

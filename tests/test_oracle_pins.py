@@ -458,3 +458,46 @@ def test_linear_mode_equals_direct_linear_convolution(orc, kind):
         assert np.max(np.abs(W[fi] - ref)) <= 1e-11 * np.max(np.abs(ref))
     # the 4 Hz wavelet is longer than the signal: the cyclic result wraps
     assert np.max(np.abs(Wc[0] - W[0])) > 0.1 * np.max(np.abs(W[0]))
+
+
+# ----------------------------------------------- sampled (user) wavelets --
+
+def test_user_wavelet_brute_force_two_ffts(orc):
+    """The two-FFT form IFFT(FFT(x_pad) FFT(psi_pad)), by numpy's FFT, for
+    random complex wavelets of odd and even length and every pad mode."""
+    rng = np.random.default_rng(5)
+    for N, w, pad in ((37, 9, "smooth7"), (50, 12, "none"), (40, 7, "linear"), (33, 33, "pow2")):
+        x = rng.normal(size=(2, N))
+        wv = rng.normal(size=(3, w)) + 1j * rng.normal(size=(3, w))
+        W = orc.cwt_user(x, wv, pad=pad)
+        L = orc.pad_length(N, pad, support=max(w // 2, w - 1 - w // 2) + 1 if pad == "linear" else None)
+        psi = np.zeros((3, L), complex)
+        for j in range(w):
+            psi[:, (j - w // 2) % L] = wv[:, j]
+        xp = np.zeros((2, L))
+        xp[:, :N] = x
+        ref = np.fft.ifft(np.fft.fft(xp)[:, None, :] * np.fft.fft(psi)[None, :, :])[:, :, :N]
+        assert np.max(np.abs(W - ref)) <= 1e-12 * np.max(np.abs(ref)), (N, w, pad)
+
+
+def test_user_wavelet_sampled_morlet_matches_closed_form(orc):
+    """Sampling the textbook time-domain Morlet over +-8 scales and passing it
+    as a user wavelet gives the closed-form path's result (the two routes of
+    "Fourier transformed formula"), up to the truncated tails (< 1e-12)."""
+    N, sfreq = 1000, 1000.0
+    freqs = np.array([10.0, 40.0])
+    sig = 7.0
+    x = synth.tones(N, sfreq, [(10.0, 1.0), (40.0, 0.5)], noise_sd=0.5, seed=3)
+    W = orc.cwt(x[None, :], sfreq, freqs, sig)[0]
+    for fi, f in enumerate(freqs):
+        s = sig / (2 * math.pi * f)
+        half = int(math.ceil(8 * s * sfreq))
+        m = np.arange(-half, half + 1)
+        # the closed form's inverse DFT is the wavelet periodised onto the
+        # circle of L = N samples: fold the sampled wavelet the same way and
+        # pass it as an L-sample user wavelet centred at L // 2
+        circ = np.zeros(N, complex)
+        np.add.at(circ, m % N, _time_morlet(m, sfreq, f, sig))
+        wv = circ[(np.arange(N) - N // 2) % N]
+        Wu = orc.cwt_user(x[None, :], wv[None, :], L=N)[0, 0]
+        assert np.max(np.abs(Wu - W[fi])) <= 1e-12 * np.max(np.abs(W[fi])), f
