@@ -145,7 +145,7 @@ typedef struct cwt_plan_desc {
     int64_t max_band_bins;   /* widest stored spectrum band                      */
     int32_t kernel;          /* 0 generic runtime-radix kernel, 1 register-resident
                                 kernel specialised for this padded length          */
-    int32_t reserved_;
+    int32_t spectrum_complex;/* 1: stored spectra are complex (sampled wavelets)  */
 } cwt_plan_desc;
 
 int cwt_plan_info(const cwt_plan *plan, cwt_plan_desc *desc);
@@ -224,7 +224,8 @@ int cwt_transform_spectra(const cwt_plan *plan, int64_t C, void *out, void *ws,
 /*
  * Copy the plan's tables to host memory for inspection (synchronises
  * `stream`).  H_host receives spectrum_bins floats (the stored bins of every
- * frequency, frequency after frequency); band_host receives 3 ints per
+ * frequency, frequency after frequency), or 2 * spectrum_bins floats
+ * (complex, interleaved) when cwt_plan_desc.spectrum_complex is 1; band_host receives 3 ints per
  * frequency (first signed bin, number of bins, offset into H_host); tw_host
  * receives 2*L floats (the twiddle table).  Any pointer may be NULL.
  */
@@ -275,6 +276,33 @@ size_t cwt_batches_workspace_size(const cwt_plan *plan, int64_t C);
 int cwt_execute_batches(const cwt_plan *plan, const float *x, int64_t x_batch_stride,
                         int32_t n_batches, int64_t C, void *out, int64_t out_batch_stride,
                         void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Plan from sampled time-domain wavelets: the two-FFT form of section
+ * "Fourier transformed formula", where a wavelet's spectrum is the DFT of its
+ * samples instead of a closed form.  wavelets: host, [n_freqs][w_len]
+ * complex64 (interleaved re, im), read during the call; sample j of each sits
+ * at time (j - w_len / 2) / sfreq, i.e. circularly at index
+ * (j - w_len / 2) mod L, and is used as given (the samples carry their own
+ * normalisation).  The transform is the cyclic convolution of the
+ * zero-padded signal with each placed wavelet.  freqs: n_freqs labels in Hz,
+ * 0 < f < sfreq / 2, used only to group frequencies into bands for
+ * band-power output.  opts as for cwt_plan_create, except that `wavelet` is
+ * not used, precision must be CWT_PREC_FP32, and CWT_PAD_LINEAR takes the
+ * wavelets' longest one-sided extent, max(w_len/2, w_len - 1 - w_len/2) + 1
+ * samples, as the support.  The spectra (1/L folded in) are computed in FP64
+ * on the GPU and rounded once; each frequency stores the shortest cyclic run
+ * of bins holding every bin of at least 1e-12 of its peak magnitude, found on
+ * the host, so this call synchronises `stream`.  These plans run
+ * cwt_execute, its two stages, cwt_execute_batches, cwt_execute_batch and
+ * cwt_plan_autotune; stream sessions reject them (CWT_E_UNSUPPORTED).
+ * Errors: those of cwt_plan_create, plus CWT_E_INVALID for wavelets == NULL,
+ * w_len < 1, w_len above the padded length or a non-finite sample, and
+ * CWT_E_UNSUPPORTED for a precision other than FP32.
+ */
+int cwt_plan_create_from_wavelets(cwt_plan **out, int64_t n, double sfreq, const double *freqs,
+                                  int32_t n_freqs, const float *wavelets, int64_t w_len,
+                                  const cwt_plan_opts *opts, void *stream);
 
 /* ---- batches ---------------------------------------------------------- */
 /*

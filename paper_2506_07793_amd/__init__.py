@@ -105,6 +105,35 @@ class Plan:
             ctypes.byref(handle), int(n), float(sfreq),
             self.freqs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(self.freqs),
             cyc_ptr, om, ctypes.byref(opts), _stream_handle(stream)))
+        self._finish(handle, out, sfreq)
+
+    @classmethod
+    def from_wavelets(cls, n, sfreq, freqs, wavelets, pad="smooth7", explicit_len=0,
+                      out="complex64", bands=None, stream=None):
+        """Plan from sampled time-domain wavelets (cwt_plan_create_from_wavelets):
+        wavelets [n_freqs, w_len] complex, sample j at time (j - w_len // 2) / sfreq,
+        used as given; freqs label the rows (band grouping)."""
+        self = cls.__new__(cls)
+        lib = _lib.load()
+        self._lib = lib
+        self.freqs = np.ascontiguousarray(np.asarray(freqs, dtype=np.float64).ravel())
+        wv = np.ascontiguousarray(np.atleast_2d(np.asarray(wavelets, dtype=np.complex64)))
+        if wv.shape[0] != len(self.freqs):
+            raise ValueError("one wavelet per frequency")
+        opts, self._edges = _make_opts(lib, "morlet", pad, explicit_len, out, "fp32", bands)
+        self._cyc = None
+        handle = ctypes.c_void_p()
+        self._ptr = None
+        _lib.check(lib.cwt_plan_create_from_wavelets(
+            ctypes.byref(handle), int(n), float(sfreq),
+            self.freqs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(self.freqs),
+            wv.view(np.float32).ctypes.data_as(ctypes.POINTER(ctypes.c_float)), wv.shape[1],
+            ctypes.byref(opts), _stream_handle(stream)))
+        self._finish(handle, out, sfreq)
+        return self
+
+    def _finish(self, handle, out, sfreq):
+        lib = self._lib
         self._ptr = handle
         desc = _lib.PlanDesc()
         _lib.check(lib.cwt_plan_info(self._ptr, ctypes.byref(desc)))
@@ -132,14 +161,18 @@ class Plan:
         return int(self._lib.cwt_workspace_size(self._ptr, int(C)))
 
     def tables(self, stream=None):
-        """(H bins [spectrum_bins] f32, band [F,3] int32, twiddles [L] complex64) on the host."""
-        H = np.empty(max(1, int(self.desc.spectrum_bins)), dtype=np.float32)
+        """(H bins [spectrum_bins] f32 (complex64 for plans from sampled wavelets),
+        band [F,3] int32, twiddles [L] complex64) on the host."""
+        cplx = bool(self.desc.spectrum_complex)
+        H = np.empty(max(1, int(self.desc.spectrum_bins)) * (2 if cplx else 1), dtype=np.float32)
         band = np.empty((self.n_freqs, 3), dtype=np.int32)
         tw = np.empty(2 * self.L, dtype=np.float32)
         _lib.check(self._lib.cwt_plan_copy_tables(
             self._ptr, H.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
             band.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
             tw.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream_handle(stream)))
+        if cplx:
+            return H.view(np.complex64)[: int(self.desc.spectrum_bins)], band, tw.view(np.complex64)
         return H[: int(self.desc.spectrum_bins)], band, tw.view(np.complex64)
 
     def batches_workspace_size(self, C):

@@ -63,7 +63,7 @@ class PlanDesc(ctypes.Structure):
         ("spectrum_bins", ctypes.c_int64),
         ("max_band_bins", ctypes.c_int64),
         ("kernel", ctypes.c_int32),
-        ("reserved_", ctypes.c_int32),
+        ("spectrum_complex", ctypes.c_int32),
     ]
 
 
@@ -134,6 +134,10 @@ SIGNATURES = {
     "cwt_plan_destroy": (ctypes.c_int, [_VP, _VP]),
     "cwt_plan_autotune": (ctypes.c_int, [_VP, _I64, _VP, ctypes.POINTER(TuneResult)]),
     "cwt_plan_timing_start": (ctypes.c_int, [_VP, _I32]),
+    "cwt_plan_create_from_wavelets": (ctypes.c_int, [ctypes.POINTER(_VP), _I64, ctypes.c_double,
+                                                     ctypes.POINTER(ctypes.c_double), _I32,
+                                                     ctypes.POINTER(ctypes.c_float), _I64,
+                                                     ctypes.POINTER(PlanOpts), _VP]),
     "cwt_batches_workspace_size": (_SZ, [_VP, _I64]),
     "cwt_execute_batches": (ctypes.c_int, [_VP, _VP, _I64, _I32, _I64, _VP, _I64, _VP, _SZ, _VP]),
     "cwt_plan_timing_stop": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float), _I32,

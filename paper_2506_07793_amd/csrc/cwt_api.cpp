@@ -417,12 +417,14 @@ static int dev_upload(T **dst, const T *src, size_t count, hipStream_t s, const 
 
 void free_plan_device(cwt_plan &P)
 {
-    void *ptrs[] = {P.d_freqs, P.d_sigmas, P.d_band, P.d_H, P.d_tw, P.d_grp_freq, P.d_grp_off};
+    void *ptrs[] = {P.d_freqs, P.d_sigmas, P.d_band, P.d_H, P.d_Hc, P.d_tw, P.d_grp_freq,
+                    P.d_grp_off};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     P.d_freqs = P.d_sigmas = nullptr;
     P.d_band = nullptr;
     P.d_H = nullptr;
+    P.d_Hc = nullptr;
     P.d_tw = nullptr;
     P.d_grp_freq = P.d_grp_off = nullptr;
 }
@@ -502,6 +504,7 @@ int enqueue_transform(const cwt_plan &P, int64_t C, void *out, void *ws, hipStre
     mp.Xh = reinterpret_cast<const float2 *>(ws);
     mp.Lh = P.L / 2 + 1;
     mp.H = P.d_H;
+    mp.Hc = P.d_Hc;
     mp.band = P.d_band;
     mp.tw = P.d_tw;
     mp.out = out;
@@ -573,6 +576,7 @@ static void fill_desc(const cwt_plan *P, cwt_plan_desc *d)
     d->spectrum_bins = P->total_bins;
     d->max_band_bins = P->max_bins;
     d->kernel = P->use_fixed ? 1 : 0;
+    d->spectrum_complex = P->user ? 1 : 0;
 }
 
 extern "C" int cwt_plan_info(const cwt_plan *P, cwt_plan_desc *d)
@@ -668,8 +672,10 @@ extern "C" int cwt_plan_copy_tables(const cwt_plan *P, float *H_host, int32_t *b
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     if (H_host && P->total_bins > 0) {
-        e = hipMemcpyAsync(H_host, P->d_H, P->total_bins * sizeof(float), hipMemcpyDeviceToHost,
-                           s);
+        e = P->user ? hipMemcpyAsync(H_host, P->d_Hc, P->total_bins * sizeof(float2),
+                                     hipMemcpyDeviceToHost, s)
+                    : hipMemcpyAsync(H_host, P->d_H, P->total_bins * sizeof(float),
+                                     hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return hip_fail(e, "copy H");
     }
     if (tw_host) {

@@ -353,6 +353,7 @@ extern "C" int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *w
         m.Xh = Xh;
         m.Lh = P.L / 2 + 1;
         m.H = P.d_H;
+        m.Hc = P.d_Hc;
         m.band = P.d_band;
         m.tw = P.d_tw;
         m.out = items[i].out;

@@ -154,7 +154,8 @@ __device__ __forceinline__ int band_p_slot(int v, int s) { return v * 256 + (s ^
 
 template <int L, int TWM>
 __device__ __forceinline__ void band_transform(const cf *__restrict__ X,
-                                               const float *__restrict__ Hf, int lo_u, int K,
+                                               const float *__restrict__ Hf,
+                                               const cf *__restrict__ Hcf, int lo_u, int K,
                                                const cf *__restrict__ tw, cf *lds, int t, cf *v_out)
 {
     constexpr int NV = L / 256;
@@ -180,7 +181,7 @@ __device__ __forceinline__ void band_transform(const cf *__restrict__ X,
             const bool upper = b > L / 2;
             cf xv = X[upper ? L - b : b];
             if (upper) xv.y = -xv.y;
-            cf z = scale(xv, Hf[k]);
+            cf z = Hcf ? mul(xv, Hcf[k]) : scale(xv, Hf[k]);
             // exp(2 pi i b 2^j / L) straight from the table (each rounded once)
             cf pw[LOG_VB + 1];
 #pragma unroll
@@ -283,12 +284,13 @@ __device__ __forceinline__ void fixed_main_row(const MainParams &p, int item)
         const int f = (MODE == kOutBand) ? p.grp_freq[q] : q;
         const BandDesc bd = p.band[f];
         const float *Hf = p.H + bd.off;
+        const cf *Hcf = p.Hc ? reinterpret_cast<const cf *>(p.Hc) + bd.off : nullptr;
         const int K = bd.K;
         const int lo_u = bd.lo < 0 ? bd.lo + L : bd.lo;
         if (q != qb) __syncthreads();  // previous transform finished with lds
         cf v[kV];
         if (K <= kBandMax) {
-            band_transform<L, TWM>(X, Hf, lo_u, K, tw, lds, t, v);
+            band_transform<L, TWM>(X, Hf, Hcf, lo_u, K, tw, lds, t, v);
         } else {
             // Band products y[k] = X~[b] H[k], b = lo + k (mod L), into lds[0, K).
             // Loads are issued unconditionally (clamped index) so that they do not
@@ -302,9 +304,8 @@ __device__ __forceinline__ void fixed_main_row(const MainParams &p, int item)
                     const int b = (lo_u + kc) & (L - 1);
                     const bool upper = b > L / 2;
                     cf xv = X[upper ? L - b : b];
-                    const float h = Hf[kc];
                     if (upper) xv.y = -xv.y;
-                    if (k < K) lds[k] = scale(xv, h);
+                    if (k < K) lds[k] = Hcf ? mul(xv, Hcf[kc]) : scale(xv, Hf[kc]);
                 }
             }
             __syncthreads();

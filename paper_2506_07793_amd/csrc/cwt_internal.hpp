@@ -32,6 +32,8 @@ struct cwt_plan {
     double *d_sigmas = nullptr;
     cwtk::BandDesc *d_band = nullptr;
     float *d_H = nullptr;
+    float2 *d_Hc = nullptr;  // complex spectra of sampled wavelets (cwt_plan_create_from_wavelets)
+    bool user = false;       // spectra from sampled wavelets
     float2 *d_tw = nullptr;
     int *d_grp_freq = nullptr;
     int *d_grp_off = nullptr;

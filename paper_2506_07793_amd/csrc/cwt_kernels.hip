@@ -66,6 +66,48 @@ hipError_t launch_generate(const GenParams &p, int max_bins, hipStream_t s)
     return hipGetLastError();
 }
 
+// ------------------------------------------------ sampled-wavelet spectra --
+
+__global__ void k_roots64(int L, double2 *roots)
+{
+    for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < L; m += gridDim.x * blockDim.x) {
+        double sn, cs;
+        sincospi(-2.0 * (double)m / (double)L, &sn, &cs);
+        roots[m] = make_double2(cs, sn);  // exp(-2 pi i m / L)
+    }
+}
+
+// Bin b of frequency f: the root index b (j - c) mod L advances by b per
+// sample, so only the first needs a division.
+__global__ void k_user_spectra(const float2 *w, int wl, int c, int L, const double2 *roots,
+                               float2 *Hd)
+{
+    const int f = blockIdx.y;
+    const float2 *wf = w + (int64_t)f * wl;
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < L; b += gridDim.x * blockDim.x) {
+        int m = (int)(((int64_t)b * (int64_t)((L - c % L) % L)) % L);  // b (0 - c) mod L
+        double re = 0.0, im = 0.0;
+        for (int j = 0; j < wl; ++j) {
+            const double2 r = roots[m];
+            const double wr = wf[j].x, wi = wf[j].y;
+            re += wr * r.x - wi * r.y;
+            im += wr * r.y + wi * r.x;
+            m += b;
+            if (m >= L) m -= L;
+        }
+        Hd[(int64_t)f * L + b] = make_float2((float)(re / L), (float)(im / L));
+    }
+}
+
+hipError_t launch_user_spectra(const float2 *w, int F, int wl, int c, int L, double2 *roots,
+                               float2 *Hd, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_roots64, dim3((L + 255) / 256), dim3(256), 0, s, L, roots);
+    hipLaunchKernelGGL(k_user_spectra, dim3((L + 255) / 256, F), dim3(256), 0, s, w, wl, c, L,
+                       roots, Hd);
+    return hipGetLastError();
+}
+
 // --------------------------------------------------------- forward FFT --
 
 // Forward transform of channel pair `pair` (channels 2 pair, 2 pair + 1).
@@ -183,6 +225,7 @@ __device__ __forceinline__ void main_task(const MainParams &p, int c, int row)
         const int f = (MODE == kOutBand) ? p.grp_freq[q] : q;
         const BandDesc bd = p.band[f];
         const float *Hf = p.H + bd.off;
+        const cf *Hcf = p.Hc ? reinterpret_cast<const cf *>(p.Hc) + bd.off : nullptr;
         const int lo = bd.lo, K = bd.K;
         auto spec_load = [=](int b) -> cf {
             int off = b - lo;
@@ -190,7 +233,6 @@ __device__ __forceinline__ void main_task(const MainParams &p, int c, int row)
             if (off >= L) off -= L;
             cf y = mk(0.f, 0.f);
             if (off < K) {
-                const float h = Hf[off];
                 cf xv;
                 if (b < Lh) {
                     xv = X[b];
@@ -198,7 +240,7 @@ __device__ __forceinline__ void main_task(const MainParams &p, int c, int row)
                     xv = X[L - b];
                     xv.y = -xv.y;
                 }
-                y = scale(xv, h);
+                y = Hcf ? mul(xv, Hcf[off]) : scale(xv, Hf[off]);
             }
             return y;
         };

@@ -45,6 +45,7 @@ struct MainParams {
     const float2 *Xh;      // [C][Lh] half spectra
     int Lh;
     const float *H;        // packed wavelet spectra (1/L folded in)
+    const float2 *Hc;      // packed complex spectra of sampled wavelets, or null
     const BandDesc *band;  // [F]
     const float2 *tw;      // [L]
     void *out;
@@ -136,6 +137,10 @@ struct LaunchEvents {
 inline size_t generic_lds_bytes(int L) { return (size_t)((L + 15) & ~15) * 8; }
 
 hipError_t launch_generate(const GenParams &p, int total_bins, hipStream_t s);
+// Spectra of sampled wavelets: Hd[f][b] = (1/L) sum_j w[f][j] exp(-2 pi i b
+// ((j - c) mod L) / L) in FP64, rounded once; roots: [L] FP64 scratch.
+hipError_t launch_user_spectra(const float2 *w, int F, int wl, int c, int L, double2 *roots,
+                               float2 *Hd, hipStream_t s);
 hipError_t launch_forward(const FwdParams &p, hipStream_t s);
 hipError_t launch_main(const MainParams &p, hipStream_t s, LaunchEvents ev = {});
 // Register-resident kernels for the padded lengths that have one.

@@ -35,6 +35,7 @@ MainParams transform_params(const cwt_plan &P, int64_t C, void *out, void *ws)
     mp.Xh = reinterpret_cast<const float2 *>(ws);
     mp.Lh = P.L / 2 + 1;
     mp.H = P.d_H;
+    mp.Hc = P.d_Hc;
     mp.band = P.d_band;
     mp.tw = P.d_tw;
     mp.out = out;

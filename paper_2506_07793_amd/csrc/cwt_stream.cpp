@@ -391,6 +391,10 @@ extern "C" int cwt_stream_open(cwt_server *srv, const cwt_plan *plan, int64_t C,
         return fail(CWT_E_INVALID, "stream sessions need a plan with CWT_OUT_BANDPOWER_F32");
     if (plan->opts.precision != CWT_PREC_FP32)
         return fail(CWT_E_UNSUPPORTED, "stream sessions run the FP32 path");
+    if (plan->user)
+        return fail(CWT_E_UNSUPPORTED,
+                    "stream sessions need a closed-form wavelet (plans from sampled wavelets "
+                    "have complex spectra)");
     const int64_t W = plan->n;
     if (C < 1 || C > 4096) return fail(CWT_E_INVALID, "C must be in [1, 4096]");
     if (hop < 1 || hop > W) return fail(CWT_E_INVALID, "hop must be in [1, n = %lld]", (long long)W);

@@ -232,3 +232,30 @@ def test_linear_edge_mode_length():
     with pytest.raises(cwt.CwtError) as e:
         cwt.describe(20000, 1000.0, [0.5], n_cycles=[10.0], pad="linear")
     assert e.value.code == _lib.CWT_E_UNSUPPORTED
+
+
+def test_sampled_wavelet_plan_validation_without_gpu():
+    """cwt_plan_create_from_wavelets rejects bad arguments before any device call."""
+    lib = _lib.load()
+    freqs = np.array([10.0, 20.0])
+    fp = freqs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    wv = np.ones((2, 8), np.complex64)
+    wp = wv.view(np.float32).ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    h = ctypes.c_void_p()
+    f = lib.cwt_plan_create_from_wavelets
+    assert f(None, 100, 1000.0, fp, 2, wp, 8, None, None) == _lib.CWT_E_INVALID
+    assert f(ctypes.byref(h), 100, 1000.0, fp, 2, None, 8, None, None) == _lib.CWT_E_INVALID
+    assert f(ctypes.byref(h), 100, 1000.0, fp, 2, wp, 0, None, None) == _lib.CWT_E_INVALID
+    assert f(ctypes.byref(h), 100, 1000.0, fp, 0, wp, 8, None, None) == _lib.CWT_E_INVALID
+    assert f(ctypes.byref(h), 0, 1000.0, fp, 2, wp, 8, None, None) == _lib.CWT_E_INVALID
+    assert f(ctypes.byref(h), 100, 1000.0, fp, 2, wp, 400, None, None) == _lib.CWT_E_INVALID  # > L
+    bad = wv.copy()
+    bad[1, 3] = np.nan
+    bp = bad.view(np.float32).ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    assert f(ctypes.byref(h), 100, 1000.0, fp, 2, bp, 8, None, None) == _lib.CWT_E_INVALID
+    o = _lib.PlanOpts()
+    lib.cwt_plan_opts_init(ctypes.byref(o))
+    o.precision = _lib.PRECISION["split_bf16"]
+    assert f(ctypes.byref(h), 100, 1000.0, fp, 2, wp, 8, ctypes.byref(o), None) == \
+        _lib.CWT_E_UNSUPPORTED
+    assert not h.value

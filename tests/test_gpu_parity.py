@@ -494,3 +494,123 @@ def test_linear_edge_mode_parity(n, sfreq):
     assert plan.L == oracle.pad_length(n, "linear", support=oracle.linear_support(sfreq, freqs, cyc))
     _parity(W, ref, "linear n=%d L=%d" % (n, plan.L))
     plan.close()
+
+
+# ------------------------------------------------- sampled (user) wavelets --
+
+def _chirp_wavelets(F, w, sfreq, seed):
+    """Arbitrary complex wavelets: Gaussian-windowed linear chirps with random
+    centre frequency, sweep, width and phase (complex spectra, not symmetric)."""
+    rng = np.random.default_rng(seed)
+    t = (np.arange(w) - w // 2) / sfreq
+    out = np.empty((F, w), np.complex128)
+    for i in range(F):
+        f0 = rng.uniform(3.0, 0.3 * sfreq)
+        sd = rng.uniform(0.2, 0.45) * (w / 2) / sfreq
+        sweep = rng.uniform(-0.5, 0.5) * f0 / (4 * sd)
+        out[i] = np.exp(-0.5 * (t / sd) ** 2) * np.exp(
+            2j * np.pi * (f0 * t + sweep * t * t) + 1j * rng.uniform(0, 2 * np.pi)) / np.sqrt(sfreq)
+    return out.astype(np.complex64)
+
+
+@pytest.mark.parametrize("n,w,pad,out", [(4096, 301, "smooth7", "complex64"), (4096, 1024, "pow2", "power"),
+                                         (1000, 251, "smooth7", "complex64"), (1000, 64, "smooth7", "bandpower"),
+                                         (2000, 401, "linear", "complex64")])
+def test_sampled_wavelet_parity(n, w, pad, out):
+    """Plans from sampled wavelets (complex spectra; register-resident and
+    runtime-radix kernels, every output mode, linear padding) against the
+    oracle's direct cyclic convolution with the placed wavelets."""
+    sfreq = 1000.0
+    F = 12
+    freqs = synth.log_freqs(2.0, 100.0, F)
+    wv = _chirp_wavelets(F, w, sfreq, n + w)
+    x = synth.eeg(2, n, sfreq, w)
+    plan = cwt.Plan.from_wavelets(n, sfreq, freqs, wv, pad=pad, out=out)
+    assert plan.desc.spectrum_complex == 1
+    W = plan.execute(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = oracle.cwt_user(x.astype(np.float64), wv.astype(np.complex128), pad=pad,
+                          L=plan.L if pad != "linear" else None)
+    assert ref.shape[-1] == n
+    if out == "complex64":
+        _parity(W, ref, "user n=%d w=%d L=%d kernel=%d" % (n, w, plan.L, plan.desc.kernel))
+    else:
+        Pr = oracle.power(ref)
+        if out == "bandpower":
+            Pr = oracle.band_power(Pr, oracle.band_groups(freqs))
+        e = np.max(np.abs(W - Pr)) / Pr.max()
+        print("user %s n=%d e=%.3e" % (out, n, e))
+        assert e <= TOL_P
+    plan.close()
+
+
+def test_sampled_wavelet_tables_and_paths():
+    """Spectra within FP32 rounding of the FP64 DFT of the placed wavelets;
+    the sampled textbook Morlet reproduces the closed-form plan; batches of
+    one plan (fused launches) equal single calls; stream sessions refuse the
+    plan."""
+    n, sfreq = 4096, 1000.0
+    freqs = np.array([8.0, 20.0, 45.0])
+    sig = 7.0
+    rng = np.random.default_rng(3)
+    # spectra against the FP64 DFT of the placed wavelets
+    wv = _chirp_wavelets(3, 333, sfreq, 9)
+    plan = cwt.Plan.from_wavelets(n, sfreq, freqs, wv)
+    H, band, _ = plan.tables()
+    ref = np.fft.fft(oracle.user_wavelet_time(wv.astype(np.complex128), plan.L), axis=1) / plan.L
+    for i in range(3):
+        lo, K, off = band[i]
+        idx = (lo + np.arange(K)) % plan.L
+        d = np.abs(H[off:off + K].astype(np.complex128) - ref[i, idx])
+        assert np.max(d) <= 2e-7 * np.abs(ref[i]).max() + 1e-30
+        mask = np.ones(plan.L, bool)
+        mask[idx] = False
+        assert np.all(np.abs(ref[i, mask]) <= 1e-12 * np.abs(ref[i]).max() * 1.01)
+    # batches through the fused launches
+    x = torch.from_numpy(synth.eeg(6, n, sfreq, 5)).cuda().view(3, 2, n)
+    refs = [plan.execute(x[i]).clone() for i in range(3)]
+    outb = torch.stack([torch.empty_like(refs[0]) for _ in range(3)])
+    plan.execute_batches(x, 3, outb, plan.alloc_batches_workspace(2), 2)
+    torch.cuda.synchronize()
+    for i in range(3):
+        assert torch.equal(outb[i], refs[i])
+    plan.close()
+    # sampled Morlet (periodised onto L) against the closed-form plan
+    t = np.arange(n)
+    rows = []
+    for f in freqs:
+        s = sig / (2 * np.pi * f)
+        half = int(np.ceil(8 * s * sfreq))
+        m = np.arange(-half, half + 1)
+        kappa = np.exp(-sig * sig / 2)
+        c = (1 + np.exp(-sig * sig) - 2 * np.exp(-0.75 * sig * sig)) ** -0.5
+        u = m / sfreq / s
+        wm = np.sqrt(1 / sfreq) * s ** -0.5 * c * np.pi ** -0.25 * np.exp(-0.5 * u * u) * (
+            np.exp(1j * sig * u) - kappa)
+        circ = np.zeros(n, complex)
+        np.add.at(circ, m % n, wm)
+        rows.append(circ[(t - n // 2) % n])
+    xs = synth.eeg(2, n, sfreq, 8)
+    pu = cwt.Plan.from_wavelets(n, sfreq, freqs, np.array(rows))
+    pc = cwt.Plan(n, sfreq, freqs, n_cycles=sig)
+    assert pu.L == pc.L == n
+    Wu = pu.execute(torch.from_numpy(xs).cuda()).cpu().numpy()
+    Wc = pc.execute(torch.from_numpy(xs).cuda()).cpu().numpy()
+    refc = oracle.cwt(xs.astype(np.float64), sfreq, freqs, sig)
+    _parity(Wu, refc, "sampled Morlet")
+    _parity(Wc, refc, "closed-form Morlet")
+    # streams need closed-form spectra
+    from paper_2506_07793_amd import stream as cstream
+    pb = cwt.Plan.from_wavelets(2000, sfreq, synth.log_freqs(1.0, 100.0, 40),
+                                _chirp_wavelets(40, 101, sfreq, 4), out="bandpower")
+    srv = cstream.Server(1 << 30)
+    with pytest.raises(cwt.CwtError) as e:
+        srv.open(pb, 4, 50)
+    assert e.value.code == _lib_codes().CWT_E_UNSUPPORTED
+    srv.close()
+    for p in (pu, pc, pb):
+        p.close()
+
+
+def _lib_codes():
+    from paper_2506_07793_amd import _lib
+    return _lib
