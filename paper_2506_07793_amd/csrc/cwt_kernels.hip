@@ -192,6 +192,106 @@ hipError_t launch_forward(const FwdParams &p, hipStream_t s)
 
 // --------------------------------------------------------- main kernel --
 
+// a / d for 0 <= a < 2^31 and d >= 1, from a double reciprocal inv = 1/d:
+// the product is within one of the quotient, and one step corrects it.
+__device__ __forceinline__ int idiv(int a, int d, double inv)
+{
+    int q = (int)((double)a * inv);
+    const int r = a - q * d;
+    if (r < 0)
+        --q;
+    else if (r >= d)
+        ++q;
+    return q;
+}
+
+// Leading passes made trivial by a narrow band.  After the passes of a
+// Stockham prefix with radix product Ns0, element J Ns0 + k of the buffer
+// (J < M = L / Ns0, k < Ns0) is the Ns0-point inverse DFT, over m, of the
+// spectrum at bins J + m M.  When the stored band spans at most M cyclically
+// consecutive bins, each such group holds at most one band bin b = J + m0 M,
+// and the element is y_b exp(2 pi i m0 k / Ns0): one complex product in place
+// of those passes.  Item g = J (Ns0 / R0) + c covers k = c R0 + kr (kr < R0),
+// which sit at elements R0 g + kr, the first pass's own output positions, so
+// the first-pass slot map keeps the writes conflict-free as there.  lo_u is
+// the band's first bin in [0, L).
+template <int R0, bool SW>
+__device__ __attribute__((noinline)) void band_prologue(const cf *__restrict__ X,
+                                                        const float *__restrict__ Hf,
+                                                        const cf *__restrict__ Hcf, int lo_u,
+                                                        int K, int L, int Lh, int Ns0, int T,
+                                                        int tid, const cf *__restrict__ tw)
+{
+    extern __shared__ cf lds[];
+    const int M = L / Ns0, nc = Ns0 / R0, n_items = L / R0;
+    const int lom = lo_u % M;
+    const double inv_nc = 1.0 / nc, inv_M = 1.0 / M, inv_Ns = 1.0 / Ns0;
+    for (int g = tid; g < n_items; g += T) {
+        const int J = idiv(g, nc, inv_nc);
+        const int c = g - J * nc;
+        int o = J - lom;
+        if (o < 0) o += M;
+        const int base = R0 * g;
+        if (o < K) {
+            int b = lo_u + o;
+            if (b >= L) b -= L;
+            cf xv;
+            if (b < Lh) {
+                xv = X[b];
+            } else {
+                xv = X[L - b];
+                xv.y = -xv.y;
+            }
+            cf y = Hcf ? mul(xv, Hcf[o]) : scale(xv, Hf[o]);
+            const int m0 = idiv(b - J, M, inv_M);  // b - J = m0 M exactly
+            const int a = m0 * c * R0;             // < Ns0^2 < 2^31
+            const int e = a - idiv(a, Ns0, inv_Ns) * Ns0;
+            y = mul(y, tw[e * M]);
+            cf w[R0];
+            twiddle_powers<R0>(tw[m0 * M], w);
+#pragma unroll
+            for (int kr = 0; kr < R0; ++kr) {
+                const int i = base + kr;
+                lds[SW ? first_pass_slot(i) : i] = kr == 0 ? y : mul(y, w[kr]);
+            }
+        } else {
+#pragma unroll
+            for (int kr = 0; kr < R0; ++kr) {
+                const int i = base + kr;
+                lds[SW ? first_pass_slot(i) : i] = mk(0.f, 0.f);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void band_prologue_rt(int R0, bool sw, const cf *X, const float *Hf,
+                                                 const cf *Hcf, int lo_u, int K, int L, int Lh,
+                                                 int Ns0, int T, int tid, const cf *tw)
+{
+    switch (R0) {
+    case 16:
+        if (sw) band_prologue<16, true>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        else band_prologue<16, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        break;
+    case 8:
+        if (sw) band_prologue<8, true>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        else band_prologue<8, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        break;
+    case 4:
+        if (sw) band_prologue<4, true>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        else band_prologue<4, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        break;
+    case 2:
+        if (sw) band_prologue<2, true>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        else band_prologue<2, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        break;
+    case 7: band_prologue<7, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw); break;
+    case 5: band_prologue<5, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw); break;
+    case 3: band_prologue<3, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw); break;
+    default: break;
+    }
+}
+
 // Output row `row` of channel c: one frequency (complex / power) or one
 // band (band power, accumulated over the band's frequencies).
 template <int MAXV, int MODE>
@@ -264,16 +364,31 @@ __device__ __forceinline__ void main_task(const MainParams &p, int c, int row)
             }
         };
 
-        int Ns = 1;
-        for (int i = 0; i < n_pass; ++i) {
+        // Leading passes the band makes trivial: while the band fits in
+        // L / (Ns R) consecutive bins (at least one pass stays, it stores).
+        int p0 = 0, Ns = 1;
+        while (p0 < n_pass - 1 && K * Ns * p.rp.radix[p0] <= L) Ns *= p.rp.radix[p0++];
+        if (p0 > 0) {
+            // a band's later frequencies reuse the buffer the previous one
+            // read last (callers separate rows with a barrier)
+            if (q != qb) __syncthreads();
+            band_prologue_rt(p.rp.radix[0], swz, X, Hf, Hcf, lo < 0 ? lo + L : lo, K, L, Lh,
+                             Ns, T, tid, tw);
+            __syncthreads();
+        }
+        // the pass that reads the first buffer written (by pass 0 or by the
+        // prologue, in the first-pass slot map when swz)
+        const int first_read = p0 > 0 ? p0 : 1;
+        for (int i = p0; i < n_pass; ++i) {
             const int R = p.rp.radix[i];
             const bool last = (i == n_pass - 1);
+            const bool sw_in = swz && i == first_read;
             if (!last) {
                 if (i == 0 && swz)
                     stockham_pass_rt<1, MAXV, true>(R, L, Ns, T, tid, tw, spec_load, lds_store_sw);
                 else if (i == 0)
                     stockham_pass_rt<1, MAXV, true>(R, L, Ns, T, tid, tw, spec_load, lds_store);
-                else if (i == 1 && swz)
+                else if (sw_in)
                     stockham_pass_rt<1, MAXV, true>(R, L, Ns, T, tid, tw, lds_load_sw, lds_store);
                 else
                     stockham_pass_rt<1, MAXV, true>(R, L, Ns, T, tid, tw, lds_load, lds_store);
@@ -281,7 +396,7 @@ __device__ __forceinline__ void main_task(const MainParams &p, int c, int row)
             } else {
                 if (i == 0)
                     stockham_pass_rt<1, MAXV, false>(R, L, Ns, T, tid, tw, spec_load, epi);
-                else if (i == 1 && swz)
+                else if (sw_in)
                     stockham_pass_rt<1, MAXV, true>(R, L, Ns, T, tid, tw, lds_load_sw, epi);
                 else
                     stockham_pass_rt<1, MAXV, true>(R, L, Ns, T, tid, tw, lds_load, epi);

@@ -614,3 +614,92 @@ def test_sampled_wavelet_tables_and_paths():
 def _lib_codes():
     from paper_2506_07793_amd import _lib
     return _lib
+
+
+def _skipped_passes(K, L, radices):
+    """Leading passes a band of K bins lets the runtime-radix kernel replace
+    by its prologue: while K <= L / (product of the radices so far)."""
+    p0, ns = 0, 1
+    while p0 < len(radices) - 1 and K * ns * radices[p0] <= L:
+        ns *= radices[p0]
+        p0 += 1
+    return p0
+
+
+@pytest.mark.parametrize("L", [98, 1000, 1680, 2187, 4116, 10000])
+@pytest.mark.parametrize("out", ["complex64", "power", "bandpower"])
+def test_generic_band_prologue(L, out):
+    """Runtime-radix kernel: rows whose band fits in L / Ns consecutive bins
+    replace the first passes (radix product Ns) by one complex product per
+    element.  The grid mixes 3-, 12- and 80-cycle wavelets from 0.3 Hz to
+    near Nyquist plus a whole-spectrum row, so that every number of replaced
+    passes from none to all but the last occurs (even and odd first radices,
+    bands wrapping past bin 0, a ragged crop); every row against the oracle."""
+    sfreq = 1000.0
+    N = L - 5
+    # 2000- and 1000-cycle rows: bands of one to three bins at every L here
+    freqs = np.concatenate([synth.log_freqs(0.3, 480.0, 24), [499.0, 20.0, 7.7]])
+    cyc = np.concatenate([np.tile([3.0, 12.0, 80.0], 8), [3.0, 2000.0, 1000.0]])
+    rng = np.random.default_rng(L + 7)
+    x = rng.normal(0, 20, size=(2, N)).astype(np.float32)
+    plan, W = _run(x, sfreq, freqs, cyc, pad="explicit", explicit_len=L, out=out)
+    assert plan.L == L and plan.desc.kernel == 0
+    rad = plan.radices
+    _, band, _ = plan.tables()
+    p0 = np.array([_skipped_passes(int(K), L, rad) for K in band[:, 1]])
+    print("L=%d radices %s skipped passes per row %s" % (L, rad, p0.tolist()))
+    assert (p0 == 0).any() and (p0 >= 1).any()
+    if L in (98, 1000, 10000):  # every pass but the storing one replaced
+        assert (p0 == len(rad) - 1).any()
+    if len(rad) >= 3:
+        assert ((p0 >= 1) & (p0 < len(rad) - 1)).any()
+    assert (band[p0 > 0, 0] < 0).any(), "no wrapped band among the replaced rows"
+    ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc, L=L)
+    if out == "complex64":
+        # per row as well, for the rows that carry signal (a wavelet far
+        # longer than the record can leave a row at 1e-60 of the peak)
+        pw = np.abs(ref) ** 2
+        for i in range(len(freqs)):
+            if pw[:, i].max() < 1e-6 * pw.max():
+                continue
+            e_P, _ = oracle.parity_errors(W[:, i], ref[:, i])
+            assert e_P <= TOL_P, (i, p0[i], e_P)
+        _parity(W, ref, "generic band prologue L=%d" % L)
+    else:
+        Pr = oracle.power(ref)
+        if out == "bandpower":
+            Pr = oracle.band_power(Pr, oracle.band_groups(freqs))
+        e = np.max(np.abs(W - Pr)) / Pr.max()
+        print("generic band prologue L=%d %s e=%.3e" % (L, out, e))
+        assert e <= TOL_P
+    plan.close()
+
+
+@pytest.mark.parametrize("L", [1000, 4116])
+def test_generic_band_prologue_sampled_wavelets(L):
+    """The prologue with complex spectra (plans from sampled wavelets).  A
+    float32 wavelet's rounding noise reaches every bin, so only wavelets with
+    exactly representable single-bin spectra have narrow bands: i^j (bin L/4)
+    and (-1)^j (bin L/2), one bin each, beside two Gaussian-windowed tones
+    whose bands cover the spectrum."""
+    sfreq = 1000.0
+    N = L - 3
+    j = np.arange(L)
+    t = (j - L // 2) / sfreq
+    wv = np.stack([1j ** (j % 4), (-1.0) ** j,
+                   np.exp(-0.5 * (t / 0.05) ** 2) * np.exp(2j * np.pi * 30.0 * t),
+                   np.exp(-0.5 * (t / 0.02) ** 2) * np.exp(2j * np.pi * 90.0 * t)]) / 50.0
+    freqs = np.array([250.0, 499.0, 30.0, 90.0])
+    x = synth.eeg(2, N, sfreq, 11)
+    plan = cwt.Plan.from_wavelets(N, sfreq, freqs, wv, pad="explicit", explicit_len=L)
+    assert plan.L == L and plan.desc.kernel == 0 and plan.desc.spectrum_complex == 1
+    _, band, _ = plan.tables()
+    p0 = [_skipped_passes(int(K), L, plan.radices) for K in band[:, 1]]
+    print("sampled L=%d bands %s skipped passes %s" % (L, band[:, :2].tolist(), p0))
+    assert band[0, 1] == 1 and band[1, 1] == 1 and p0[0] == len(plan.radices) - 1
+    W = plan.execute(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = oracle.cwt_user(x.astype(np.float64), wv.astype(np.complex64).astype(np.complex128),
+                          pad="explicit", L=L)
+    for i in range(4):
+        _parity(W[:, i], ref[:, i], "sampled generic band prologue L=%d row %d" % (L, i))
+    plan.close()
