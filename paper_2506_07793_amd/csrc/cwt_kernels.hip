@@ -120,7 +120,8 @@ __device__ __forceinline__ void forward_task(const FwdParams &p, int pair)
     const bool has1 = (c0 + 1) < p.C;
     const float *x0 = p.x + (int64_t)c0 * p.x_stride;
     const float *x1 = p.x + (int64_t)(c0 + 1) * p.x_stride;
-    const cf *tw = reinterpret_cast<const cf *>(p.tw);
+    const gptr<cf> tw = as_global(reinterpret_cast<const cf *>(p.tw));
+    const gptr<float> x0g = as_global(x0), x1g = as_global(x1);
     const int N = p.N;
 
     auto lds_load = [](int idx) -> cf { return lds[idx]; };
@@ -131,8 +132,8 @@ __device__ __forceinline__ void forward_task(const FwdParams &p, int pair)
     auto in_load = [=](int idx) -> cf {
         cf z = mk(0.f, 0.f);
         if (idx < N) {
-            z.x = x0[idx];
-            if (has1) z.y = x1[idx];
+            z.x = x0g[idx];
+            if (has1) z.y = x1g[idx];
         }
         return z;
     };
@@ -216,11 +217,10 @@ __device__ __forceinline__ int idiv(int a, int d, double inv)
 // the first-pass slot map keeps the writes conflict-free as there.  lo_u is
 // the band's first bin in [0, L).
 template <int R0, bool SW>
-__device__ __attribute__((noinline)) void band_prologue(const cf *__restrict__ X,
-                                                        const float *__restrict__ Hf,
-                                                        const cf *__restrict__ Hcf, int lo_u,
-                                                        int K, int L, int Lh, int Ns0, int T,
-                                                        int tid, const cf *__restrict__ tw)
+__device__ __attribute__((noinline)) void band_prologue(gptr<cf> X, gptr<float> Hf,
+                                                        gptr<cf> Hcf, int lo_u, int K, int L,
+                                                        int Lh, int Ns0, int T, int tid,
+                                                        gptr<cf> tw)
 {
     extern __shared__ cf lds[];
     const int M = L / Ns0, nc = Ns0 / R0, n_items = L / R0;
@@ -237,18 +237,18 @@ __device__ __attribute__((noinline)) void band_prologue(const cf *__restrict__ X
             if (b >= L) b -= L;
             cf xv;
             if (b < Lh) {
-                xv = X[b];
+                xv = load_cf(X + b);
             } else {
-                xv = X[L - b];
+                xv = load_cf(X + (L - b));
                 xv.y = -xv.y;
             }
-            cf y = Hcf ? mul(xv, Hcf[o]) : scale(xv, Hf[o]);
+            cf y = Hcf ? mul(xv, load_cf(Hcf + o)) : scale(xv, Hf[o]);
             const int m0 = idiv(b - J, M, inv_M);  // b - J = m0 M exactly
             const int a = m0 * c * R0;             // < Ns0^2 < 2^31
             const int e = a - idiv(a, Ns0, inv_Ns) * Ns0;
-            y = mul(y, tw[e * M]);
+            y = mul(y, load_cf(tw + e * M));
             cf w[R0];
-            twiddle_powers<R0>(tw[m0 * M], w);
+            twiddle_powers<R0>(load_cf(tw + m0 * M), w);
 #pragma unroll
             for (int kr = 0; kr < R0; ++kr) {
                 const int i = base + kr;
@@ -264,9 +264,9 @@ __device__ __attribute__((noinline)) void band_prologue(const cf *__restrict__ X
     }
 }
 
-__device__ __forceinline__ void band_prologue_rt(int R0, bool sw, const cf *X, const float *Hf,
-                                                 const cf *Hcf, int lo_u, int K, int L, int Lh,
-                                                 int Ns0, int T, int tid, const cf *tw)
+__device__ __forceinline__ void band_prologue_rt(int R0, bool sw, gptr<cf> X, gptr<float> Hf,
+                                                 gptr<cf> Hcf, int lo_u, int K, int L, int Lh,
+                                                 int Ns0, int T, int tid, gptr<cf> tw)
 {
     switch (R0) {
     case 16:
@@ -301,7 +301,7 @@ __device__ __forceinline__ void main_task(const MainParams &p, int c, int row)
     const int L = p.rp.L, T = blockDim.x, tid = threadIdx.x;
     const int N = p.N, Lh = p.Lh;
     const int n_pass = p.rp.n_pass;
-    const cf *tw = reinterpret_cast<const cf *>(p.tw);
+    const gptr<cf> tw = as_global(reinterpret_cast<const cf *>(p.tw));
     int qb, qe;
     if (MODE == kOutBand) {
         qb = p.grp_off[row];
@@ -310,7 +310,7 @@ __device__ __forceinline__ void main_task(const MainParams &p, int c, int row)
         qb = row;
         qe = row + 1;
     }
-    const cf *X = reinterpret_cast<const cf *>(p.Xh) + (int64_t)c * Lh;
+    const gptr<cf> X = as_global(reinterpret_cast<const cf *>(p.Xh) + (int64_t)c * Lh);
 
     float *orow_band = reinterpret_cast<float *>(p.out) + ((int64_t)c * p.n_rows + row) * N;
     const float inv_n = 1.0f / (float)(qe - qb);
@@ -324,8 +324,9 @@ __device__ __forceinline__ void main_task(const MainParams &p, int c, int row)
     for (int q = qb; q < qe; ++q) {
         const int f = (MODE == kOutBand) ? p.grp_freq[q] : q;
         const BandDesc bd = p.band[f];
-        const float *Hf = p.H + bd.off;
-        const cf *Hcf = p.Hc ? reinterpret_cast<const cf *>(p.Hc) + bd.off : nullptr;
+        const gptr<float> Hf = as_global(p.H + bd.off);
+        const gptr<cf> Hcf =
+            p.Hc ? as_global(reinterpret_cast<const cf *>(p.Hc) + bd.off) : nullptr;
         const int lo = bd.lo, K = bd.K;
         auto spec_load = [=](int b) -> cf {
             int off = b - lo;
@@ -335,31 +336,36 @@ __device__ __forceinline__ void main_task(const MainParams &p, int c, int row)
             if (off < K) {
                 cf xv;
                 if (b < Lh) {
-                    xv = X[b];
+                    xv = load_cf(X + b);
                 } else {
-                    xv = X[L - b];
+                    xv = load_cf(X + (L - b));
                     xv.y = -xv.y;
                 }
-                y = Hcf ? mul(xv, Hcf[off]) : scale(xv, Hf[off]);
+                y = Hcf ? mul(xv, load_cf(Hcf + off)) : scale(xv, Hf[off]);
             }
             return y;
         };
-        float2 *ocx = reinterpret_cast<float2 *>(p.out) + ((int64_t)c * p.n_rows + f) * N;
-        float *opw = reinterpret_cast<float *>(p.out) + ((int64_t)c * p.n_rows + f) * N;
-        // Band mode accumulates in the output row, which only this
-        // workgroup touches; every thread revisits the same samples t for
-        // each frequency, so it reads back its own earlier writes.
-        const bool first = (q == qb), final_f = (q == qe - 1);
-        auto epi = [=](int, int t, cf v) {
+        // Output row of this frequency (band mode: of the band, accumulated
+        // over its frequencies; only this workgroup touches it, and every
+        // thread revisits the same samples t for each frequency, so it reads
+        // back its own earlier writes).  The store functor carries five
+        // registers (row pointer, n, flags, 1/count) so that it is passed to
+        // the out-of-line last pass in registers rather than through memory.
+        const gptr_mut<float> orow = as_global_mut(
+            (MODE == kOutBand) ? orow_band
+                               : reinterpret_cast<float *>(p.out) +
+                                     ((int64_t)c * p.n_rows + f) * N * (MODE == kOutComplex ? 2 : 1));
+        const int eflags = (q == qb ? 1 : 0) | (q == qe - 1 ? 2 : 0);
+        auto epi = [orow, N, eflags, inv_n](int, int t, cf v) {
             if (t < N) {
                 const float pw = v.x * v.x + v.y * v.y;
                 if (MODE == kOutComplex) {
-                    ocx[t] = make_float2(v.x, v.y);
+                    reinterpret_cast<gptr_mut<f2_t>>(orow)[t] = f2_t{v.x, v.y};
                 } else if (MODE == kOutPower) {
-                    opw[t] = pw;
+                    orow[t] = pw;
                 } else {
-                    float a = first ? pw : orow_band[t] + pw;
-                    orow_band[t] = final_f ? a * inv_n : a;
+                    const float a = (eflags & 1) ? pw : orow[t] + pw;
+                    orow[t] = (eflags & 2) ? a * inv_n : a;
                 }
             }
         };

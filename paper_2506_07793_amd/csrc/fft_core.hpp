@@ -24,6 +24,34 @@ struct alignas(8) cf {
 };
 
 __device__ __forceinline__ cf mk(float a, float b) { return cf{a, b}; }
+
+// Pointers into device (global) memory.  Out-of-line functions do not see
+// where a plain pointer points and access it with flat instructions, whose
+// completion is counted together with the LDS accesses', so that every wait
+// for LDS data would also wait for the outstanding memory loads; pointers of
+// the global address space keep those accesses on the global path.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T *;
+template <class T>
+using gptr_mut = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(const T *p)
+{
+    return (gptr<T>)p;
+}
+template <class T>
+__device__ __forceinline__ gptr_mut<T> as_global_mut(T *p)
+{
+    return (gptr_mut<T>)p;
+}
+// Complex values move through a two-float vector type, which (unlike a
+// struct) copies out of and into a qualified address space directly.
+typedef float f2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cf load_cf(gptr<cf> p)
+{
+    const f2_t v = *reinterpret_cast<gptr<f2_t>>(p);
+    return cf{v.x, v.y};
+}
 __device__ __forceinline__ cf add(cf a, cf b) { return cf{a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ cf sub(cf a, cf b) { return cf{a.x - b.x, a.y - b.y}; }
 __device__ __forceinline__ cf mul(cf a, cf b)
@@ -243,8 +271,7 @@ __device__ __forceinline__ void twiddle_powers(cf w1, cf *w)
 // every radix keeps one pass's registers live at a time.
 template <int R, int SIGN, int MAXV, bool SYNC_MID, class Load, class Store>
 __device__ __attribute__((noinline)) void stockham_pass(int L, int Ns, int T, int tid,
-                                                        const cf *__restrict__ tw, Load load,
-                                                        Store store)
+                                                        gptr<cf> tw, Load load, Store store)
 {
     constexpr int MB = MaxB<R, MAXV>::value;
     const int S = L / R;
@@ -273,7 +300,7 @@ __device__ __attribute__((noinline)) void stockham_pass(int L, int Ns, int T, in
         if (j < S) {
             if (Ns > 1) {
                 cf w[R];
-                twiddle_powers<R>(conj_if<SIGN>(tw[(unsigned)(jm * twstep)]), w);
+                twiddle_powers<R>(conj_if<SIGN>(load_cf(tw + (unsigned)(jm * twstep))), w);
 #pragma unroll
                 for (int r = 1; r < R; ++r) v[k][r] = mul(v[k][r], w[r]);
             }
@@ -288,8 +315,7 @@ __device__ __attribute__((noinline)) void stockham_pass(int L, int Ns, int T, in
 // Dispatch one pass of runtime radix R to its compiled form.
 template <int SIGN, int MAXV, bool SYNC_MID, class Load, class Store>
 __device__ __forceinline__ void stockham_pass_rt(int R, int L, int Ns, int T, int tid,
-                                                 const cf *__restrict__ tw, Load load,
-                                                 Store store)
+                                                 gptr<cf> tw, Load load, Store store)
 {
     switch (R) {
     case 16: stockham_pass<16, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
