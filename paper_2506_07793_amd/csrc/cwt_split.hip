@@ -11,7 +11,7 @@
 // magnitude in [2^14, 2^15) (FP16 range; undone exactly after the MFMA); BF16
 // keeps FP32's exponent range and is not scaled.  Twiddles are applied in
 // FP32 on the VALU when a stage stores its outputs; the DFT constants and
-// twiddles are FP64 values rounded once.  The forward transform of the
+// twiddles are FP64 values rounded once (the plan's twiddle table).  The forward transform of the
 // channels is the FP32 path's.
 #include "cwt_internal.hpp"
 #include "fft_core.hpp"
@@ -66,7 +66,8 @@ struct SplitOps<CWT_PREC_SPLIT_BF16> {
 __device__ __forceinline__ int fp16_exponent(float m)
 {
     if (!(m > 0.f)) return 0;
-    return 14 - ilogbf(m);
+    // m = f 2^e with f in [0.5, 1), so floor(log2 m) = e - 1
+    return 15 - __builtin_amdgcn_frexp_expf(m);
 }
 
 }  // namespace
@@ -78,6 +79,7 @@ __global__ void __launch_bounds__(kT) k_split_main(MainParams p)
     typedef typename Ops::vec vec;
     typedef typename Ops::scalar sc;
     __shared__ cf lds[kL];
+    __shared__ cf root16[16];  // exp(2 pi i e / 16), from the twiddle table
     float *ldsf = reinterpret_cast<float *>(lds);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -85,16 +87,20 @@ __global__ void __launch_bounds__(kT) k_split_main(MainParams p)
     const int N = p.N;
     const cf *tw = reinterpret_cast<const cf *>(p.tw);
 
-    // DFT operands of this lane: row m = n, columns k = 8 q + i.
+    if (tid < 16) root16[tid] = tw[tid * (kL / 16)];
+    __syncthreads();
+
+    // DFT operands of this lane: row m = n, columns k = 8 q + i, from the
+    // 16th roots of unity of the twiddle table (FP64 values rounded once).
     vec ar_hi, ar_lo, ai_hi, ai_lo;
+#pragma unroll
     for (int i = 0; i < 8; ++i) {
         const int k = 8 * q + i;
         const int r = k & 15;
-        double sn, cs;
-        sincospi(2.0 * (double)((n * r) & 15) / 16.0, &sn, &cs);
+        const cf w = root16[(n * r) & 15];
         // columns 0..15 multiply Xr, 16..31 multiply Xi
-        const float fr = (k < 16) ? (float)cs : (float)(-sn);
-        const float fi = (k < 16) ? (float)sn : (float)cs;
+        const float fr = (k < 16) ? w.x : -w.y;
+        const float fi = (k < 16) ? w.y : w.x;
         sc h, l;
         Ops::split(fr, h, l);
         ar_hi[i] = h;
@@ -129,8 +135,37 @@ __global__ void __launch_bounds__(kT) k_split_main(MainParams p)
         const bool first = (qq == qb), final_f = (qq == qe - 1);
         if (qq != qb) __syncthreads();
 
-        int Ns = 1;
+        // A band of at most L/16 bins leaves one nonzero input in each
+        // first-stage butterfly (the 16 inputs j + 256 r lie 256 bins apart):
+        // its outputs are that input times exp(2 pi i r0 k / 16), written here
+        // in FP32 with the second stage's twiddle folded in, and the MFMA
+        // stages start at the second.
+        const bool band = K <= kL / 16;
+        if (band) {
+#pragma unroll 1
+            for (int m = 0; m < kL / kT; ++m) {
+                const int d = tid + kT * m;  // first-stage output slot 16 j + k
+                const int j = d >> 4, k = d & 15;
+                const int o = (j - lo_u) & 255;  // band offset of the bin = j mod 256
+                cf val = mk(0.f, 0.f);
+                if (o < K) {
+                    const int b = (lo_u + o) & (kL - 1);
+                    const bool upper = b > kL / 2;
+                    cf xv = X[upper ? kL - b : b];
+                    if (upper) xv.y = -xv.y;
+                    // exp(2 pi i r0 k / 16) of input r0 = b div 256, then the
+                    // second stage's twiddle of slot d (d div 256 = m)
+                    const cf y = mul(scale(xv, Hf[o]), root16[((b >> 8) * k) & 15]);
+                    val = mul(y, tw[(16 * k * m) & (kL - 1)]);
+                }
+                lds[d] = val;
+            }
+            __syncthreads();
+        }
+#pragma unroll
         for (int s = 0; s < 3; ++s) {
+            const int Ns = 1 << (4 * s);
+            if (s == 0 && band) continue;
             f4 dr[4], di[4];
             int ex[4];
 #pragma unroll
@@ -213,7 +248,6 @@ __global__ void __launch_bounds__(kT) k_split_main(MainParams p)
                 }
             }
             if (s < 2) __syncthreads();
-            Ns *= 16;
         }
     }
 }

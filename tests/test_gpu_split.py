@@ -77,3 +77,28 @@ def test_split_needs_length_4096():
     with pytest.raises(cwt.CwtError) as ei:
         cwt.Plan(1000, 1000.0, [10.0, 20.0], n_cycles=5.0, precision="split_f16")
     assert ei.value.code == _lib.CWT_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", ["split_f16", "split_bf16"])
+def test_split_band_first_stage(prec):
+    """Rows whose band has at most L/16 = 256 bins compute the first stage
+    directly (one input per butterfly) and run the MFMA stages from the
+    second; wider rows run all three.  Grid as in the register-resident band
+    test: bands of 1 to 256 bins, wrapping past bin 0, ending at the last
+    positive bin, and whole-spectrum rows; every row against the oracle."""
+    sfreq, L = 1000.0, 4096
+    N = L - 37
+    freqs = np.concatenate([synth.log_freqs(0.3, 480.0, 20), [499.0, 495.0]])
+    cyc = np.concatenate([np.where(np.arange(20) % 2 == 0, 3.0, 12.0), [3.0, 240.0]])
+    rng = np.random.default_rng(17)
+    x = rng.normal(0, 20, size=(2, N)).astype(np.float32)
+    plan = cwt.Plan(N, sfreq, freqs, n_cycles=cyc, pad="pow2", precision=prec)
+    _, band, _ = plan.tables()
+    K = band[:, 1]
+    assert (K <= 256).any() and (K > 256).any() and (band[K <= 256, 0] < 0).any()
+    got = plan.execute(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc, L=L)
+    e_P, e_W = oracle.parity_errors(got, ref)
+    print("%s band first stage: e_P=%.3e e_W=%.3e" % (prec, e_P, e_W))
+    assert e_P <= BOUND[prec]
+    plan.close()
