@@ -1,13 +1,17 @@
 // Batched form of libcwt: recordings of uneven length, channel count and
-// frequency grid in one graph launch of persistent kernels.
+// frequency grid in one graph launch.
 //
 // The host builds, in the caller's workspace, a parameter table per item and
-// two task lists (channel pairs for the forward transforms, (channel, row)
-// for the transforms), sorted by estimated cost so that the long tasks start
-// first.  Tasks are grouped into classes by workgroup size; each class runs
-// one persistent forward kernel and one persistent transform kernel whose
-// workgroups claim tasks through an atomic counter.  The launches are
-// captured once into a HIP graph per (workspace, layout) and replayed.
+// two task lists (channel pairs for the forward transforms, runs of output
+// rows of one channel for the transforms), sorted by estimated cost so that
+// the long tasks start first.  Tasks are grouped into classes by workgroup
+// size; each class runs one persistent forward kernel whose workgroups claim
+// tasks through an atomic counter, and one transform kernel: persistent in
+// the same way for the 16-value classes, one row per workgroup (handed out
+// by the hardware dispatcher, one class per output mode) for the 24-value
+// classes, whose persistent kernel would not fit in its registers.  The
+// launches are captured once into a HIP graph per (workspace, layout) and
+// replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,8 +47,13 @@ int class_threads(int t)
 struct ClassInfo {
     int threads = 0, maxv = 16;
     int max_L = 1;
+    // 24-value classes run one row per workgroup (k_batch_rows, one output
+    // mode per class): their persistent kernel would spill registers
+    bool rows = false;
+    int mode = -1;
     std::vector<BatchTask> fwd, main;
     std::vector<double> fwd_cost, main_cost;  // sort keys (larger first)
+    double total = 0;                          // sum of main_cost
 };
 
 // Estimated cost of one transform row of a plan: L log2 L (FFT work).
@@ -211,9 +220,14 @@ int enqueue_kernels(const std::vector<ClassInfo> &classes, char *ws, const Layou
                                  reinterpret_cast<const BatchTask *>(ws + Lo.fwd_tasks) + f_off,
                                  (int)c.fwd.size(), ctr, c.threads, c.maxv, lds, sk);
         if (e != hipSuccess) return hip_fail(e, "batch forward launch");
-        e = launch_batch_main(reinterpret_cast<const MainParams *>(ws + Lo.main_items),
-                              reinterpret_cast<const BatchTask *>(ws + Lo.main_tasks) + m_off,
-                              (int)c.main.size(), ctr + 1, c.threads, c.maxv, lds, sk);
+        if (c.rows)
+            e = launch_batch_rows(reinterpret_cast<const MainParams *>(ws + Lo.main_items),
+                                  reinterpret_cast<const BatchTask *>(ws + Lo.main_tasks) + m_off,
+                                  (int)c.main.size(), c.threads, c.maxv, c.mode, lds, sk);
+        else
+            e = launch_batch_main(reinterpret_cast<const MainParams *>(ws + Lo.main_items),
+                                  reinterpret_cast<const BatchTask *>(ws + Lo.main_tasks) + m_off,
+                                  (int)c.main.size(), ctr + 1, c.threads, c.maxv, lds, sk);
         if (e != hipSuccess) return hip_fail(e, "batch transform launch");
         if (fork) {
             e = hipEventRecord(fk->join[k], sk);
@@ -252,15 +266,19 @@ extern "C" int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *w
     if (((uintptr_t)ws & 255) != 0) return fail(CWT_E_INVALID, "ws must be 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
 
-    // Tasks, grouped by workgroup-size class.
-    std::map<std::pair<int, int>, ClassInfo> by_class;
+    // Tasks, grouped by workgroup-size class (and output mode for the
+    // one-row-per-workgroup classes).
+    std::map<std::tuple<int, int, int>, ClassInfo> by_class;
     for (int i = 0; i < n; ++i) {
         const cwt_plan &P = *items[i].plan;
         if (items[i].C == 0) continue;
         const int thr = class_threads(P.rp.threads);
-        ClassInfo &c = by_class[{thr, P.rp.maxv}];
+        const bool one_row = P.rp.maxv > 16;
+        ClassInfo &c = by_class[{thr, P.rp.maxv, one_row ? (int)P.opts.out : -1}];
         c.threads = thr;
         c.maxv = P.rp.maxv;
+        c.rows = one_row;
+        c.mode = one_row ? (int)P.opts.out : -1;
         c.max_L = std::max(c.max_L, P.L);
         const int rows = (P.opts.out == CWT_OUT_BANDPOWER_F32) ? P.n_bands : P.F;
         const double rc = row_cost(P);
@@ -276,12 +294,14 @@ extern "C" int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *w
             for (int r = 0; r < rows;) {
                 int nr = 0;
                 double cost = 0;
-                while (r + nr < rows && (nr == 0 || cost + freqs_in(r + nr) * rc <= kTaskCost)) {
+                while (r + nr < rows &&
+                       (nr == 0 || (!c.rows && cost + freqs_in(r + nr) * rc <= kTaskCost))) {
                     cost += freqs_in(r + nr) * rc;
                     ++nr;
                 }
                 c.main.push_back({i, ch, r, nr});
                 c.main_cost.push_back(cost);
+                c.total += cost;
                 r += nr;
             }
     }
@@ -304,7 +324,14 @@ extern "C" int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *w
         n_main += c.main.size();
         classes.push_back(std::move(c));
     }
+    // The costliest class first: it is the critical path, and the classes
+    // launched after it fill the CUs it leaves free.
+    std::stable_sort(classes.begin(), classes.end(),
+                     [](const ClassInfo &a, const ClassInfo &b) { return a.total > b.total; });
     if (classes.size() > 32) return fail(CWT_E_UNSUPPORTED, "too many task classes");
+    for (const ClassInfo &c : classes)
+        if (c.main.size() > (size_t)INT32_MAX || c.fwd.size() > (size_t)INT32_MAX)
+            return fail(CWT_E_UNSUPPORTED, "too many tasks in one class");
     const Layout Lo = make_layout(items, n, n_fwd, n_main);
     if (ws_bytes < Lo.total)
         return fail(CWT_E_INVALID, "workspace too small: %zu < %zu bytes", ws_bytes, Lo.total);
@@ -376,7 +403,7 @@ extern "C" int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *w
         ft += c.fwd.size();
         std::copy(c.main.begin(), c.main.end(), mt);
         mt += c.main.size();
-        shape.insert(shape.end(), {c.threads, c.maxv, c.max_L, (int64_t)c.fwd.size(),
+        shape.insert(shape.end(), {c.threads, c.maxv, c.max_L, c.mode, (int64_t)c.fwd.size(),
                                    (int64_t)c.main.size()});
     }
     shape.insert(shape.end(), {(int64_t)Lo.total, n});

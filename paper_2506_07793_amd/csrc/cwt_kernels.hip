@@ -294,8 +294,8 @@ __device__ __forceinline__ void band_prologue_rt(int R0, bool sw, gptr<cf> X, gp
 
 // Output row `row` of channel c: one frequency (complex / power) or one
 // band (band power, accumulated over the band's frequencies).
-template <int MAXV, int MODE>
-__device__ __forceinline__ void main_task(const MainParams &p, int c, int row)
+template <int MAXV, int MODE, class P = MainParams>
+__device__ __forceinline__ void main_task(const P &p, int c, int row)
 {
     extern __shared__ cf lds[];
     const int L = p.rp.L, T = blockDim.x, tid = threadIdx.x;
@@ -468,6 +468,23 @@ __global__ void __launch_bounds__(1024)
     }
 }
 
+// One output row per workgroup, for the batch classes whose persistent
+// kernel would not fit in its registers (with a task loop around them the
+// passes of a 1024-thread, 24-value workgroup spill): the hardware dispatcher
+// hands out the rows, longest first in table order.  The parameter table is
+// read through the constant address space, so that its fields may be loaded
+// again after each out-of-line pass instead of being held in registers.
+template <int MAXV, int MODE>
+__global__ void __launch_bounds__(1024)
+    k_batch_rows(const MainParams *items, const BatchTask *rows)
+{
+    typedef const __attribute__((address_space(4))) MainParams CMP;
+    typedef const __attribute__((address_space(4))) BatchTask CBT;
+    CBT &tk = *(CBT *)(rows + blockIdx.x);
+    CMP &p = *(CMP *)(items + tk.item);
+    main_task<MAXV, MODE>(p, (int)tk.a, (int)tk.b);
+}
+
 __global__ void k_zero_counters(int *c, int n)
 {
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
@@ -526,6 +543,33 @@ hipError_t launch_batch_main(const MainParams *items, const BatchTask *tasks, in
                            counter);
     }
     return hipGetLastError();
+}
+
+template <int MAXV, int MODE>
+static hipError_t launch_batch_rows_t(const MainParams *items, const BatchTask *rows, int n,
+                                      int threads, size_t lds, hipStream_t s)
+{
+    set_lds_limit((const void *)k_batch_rows<MAXV, MODE>, lds);
+    hipLaunchKernelGGL((k_batch_rows<MAXV, MODE>), dim3(n), dim3(threads), lds, s, items, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_rows(const MainParams *items, const BatchTask *rows, int n, int threads,
+                             int maxv, int mode, size_t lds, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    if (maxv <= 16) {
+        switch (mode) {
+        case kOutComplex: return launch_batch_rows_t<16, kOutComplex>(items, rows, n, threads, lds, s);
+        case kOutPower: return launch_batch_rows_t<16, kOutPower>(items, rows, n, threads, lds, s);
+        default: return launch_batch_rows_t<16, kOutBand>(items, rows, n, threads, lds, s);
+        }
+    }
+    switch (mode) {
+    case kOutComplex: return launch_batch_rows_t<24, kOutComplex>(items, rows, n, threads, lds, s);
+    case kOutPower: return launch_batch_rows_t<24, kOutPower>(items, rows, n, threads, lds, s);
+    default: return launch_batch_rows_t<24, kOutBand>(items, rows, n, threads, lds, s);
+    }
 }
 
 template <int MAXV, int MODE>

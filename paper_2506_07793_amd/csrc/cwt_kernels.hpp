@@ -73,6 +73,10 @@ hipError_t launch_batch_forward(const FwdParams *items, const BatchTask *tasks, 
                                 int *counter, int threads, int maxv, size_t lds, hipStream_t s);
 hipError_t launch_batch_main(const MainParams *items, const BatchTask *tasks, int n,
                              int *counter, int threads, int maxv, size_t lds, hipStream_t s);
+// One workgroup per task of exactly one row (tasks[k].n == 1), all of one
+// output mode; n workgroups.
+hipError_t launch_batch_rows(const MainParams *items, const BatchTask *rows, int n, int threads,
+                             int maxv, int mode, size_t lds, hipStream_t s);
 
 // ----------------------------------------------------------- streaming --
 // One completed hop of one session.
