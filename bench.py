@@ -6,7 +6,9 @@ Workload (one step = the whole hot path on one batch, inputs resident in HBM):
 10 Hz alpha bursts, seed 2), 100 log-spaced frequencies 1-100 Hz,
 n_cycles = clip(f/2, 3, 10), FP32 input, complex64 output [64, 100, 4096]:
 forward real FFT of every channel, then per (channel, frequency) the spectral
-multiply, inverse FFT, crop and store.  By default the K timed steps run as
+multiply, inverse FFT, crop and store.  Each step writes its own 210 MB output
+buffer of a 64-buffer ring (13.4 GB, beyond the 256 MB last-level cache), so
+that the outputs reach HBM.  By default the K timed steps run as
 cwt_execute_batches: one launch per step that transforms the step's batch and
 computes the next batch's forward FFT (--serial: forward + transform launches
 per step; the serial step time is reported either way).
@@ -390,18 +392,42 @@ def main():
     ws = plan.alloc_workspace(C, device=dev)
     stream = torch.cuda.Stream()  # default priority
 
+    # Every step runs the whole path on one batch (the same resident input)
+    # and writes its own output buffer: the steps cycle through a ring of
+    # RING output buffers (13.4 GB), far beyond the 256 MB last-level cache,
+    # so that every step's output reaches HBM.  Overwriting one 210 MB buffer
+    # each step can be partly absorbed by that cache (on some boxes it is);
+    # that form is timed too and reported beside (`one_output_buffer`).
+    ob = plan.output_bytes(C)
+    RING = 64
+    ring = torch.empty(RING * ob, dtype=torch.uint8, device=dev)
+    slot = [0]
+
     def step():
         plan.forward_spectra(x, ws, stream=stream)
-        plan.transform_spectra(C, out, ws, stream=stream)
+        i = slot[0]
+        plan.transform_spectra(C, ring[i * ob:(i + 1) * ob], ws, stream=stream)
+        slot[0] = (i + 1) % RING
 
     # Pipelined form (cwt_execute_batches): one launch per step that
     # transforms this step's batch and computes the next batch's forward FFT
-    # into the other half of a double-buffered workspace.  Every step still
-    # runs the whole path on one batch; the batches are the same resident
-    # input (stride 0) and overwrite one output buffer (stride 0).
+    # into the other half of a double-buffered workspace; one call per pass
+    # over the ring (its last step has no next batch to fuse).
     wsb = plan.alloc_batches_workspace(C, device=dev)
 
+    def chunks(n):
+        out_n = []
+        while n > 0:
+            out_n.append(min(RING, n))
+            n -= out_n[-1]
+        return out_n
+
     def batches(n):
+        for m in chunks(n):
+            plan.execute_batches(x, m, ring, wsb, C, x_batch_stride=0, out_batch_stride=ob,
+                                 stream=stream)
+
+    def batches_one_buffer(n):
         plan.execute_batches(x, n, out, wsb, C, x_batch_stride=0, out_batch_stride=0,
                              stream=stream)
 
@@ -431,6 +457,7 @@ def main():
         # cwt_execute_batches call); --serial: K forward + transform pairs;
         # --graph 1: K replays of a captured forward + transform step.
         if args.graph:
+            # (a captured step writes the ring slot it was captured with)
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g, stream=stream):
                 step()
@@ -465,14 +492,25 @@ def main():
         assert len(kernel_ms) == K, "timed %d of %d transform launches" % (len(kernel_ms), K)
         fused = not (args.graph or serial) and plan.desc.kernel == 1 and K > 1
         if fused:
-            kernel_ms = kernel_ms[:-1]  # the last step has no next batch to fuse
+            # the last step of each call has no next batch to fuse
+            ends = set(np.cumsum(chunks(K)) - 1)
+            kernel_ms = np.array([m for i, m in enumerate(kernel_ms) if i not in ends])
         ms_main = float(np.mean(kernel_ms))
 
-        # Store ceiling: a plain device fill of the same output buffer.
-        fill = out.view(torch.float32)
-        for _ in range(3):
-            fill.fill_(0.0)
-        ms_fill = timed(lambda: [fill.fill_(0.0) for _ in range(K)]) / K
+        # Store ceiling: a plain device fill of one output buffer per step,
+        # cycling through the ring like the steps.
+        fills = [ring[i * ob:(i + 1) * ob].view(torch.float32) for i in range(RING)]
+        for f_ in fills[:3]:
+            f_.fill_(0.0)
+        ms_fill = timed(lambda: [fills[i % RING].fill_(0.0) for i in range(K)]) / K
+
+        # The same pipelined steps overwriting one output buffer.
+        one_buf = None
+        if not (args.graph or serial):
+            batches_one_buffer(K)
+            ms_one = timed(lambda: batches_one_buffer(K)) / K
+            one_buf = {"ms_per_step": ms_one, "value": C * F * N / (ms_one * 1e-3),
+                       "MB": ob / 1e6}
 
     pts = C * F * N
     value = pts / (ms_step * 1e-3)
@@ -518,6 +556,8 @@ def main():
                      "median_ms": float(np.median(kernel_ms)),
                      "p90_ms": float(np.percentile(kernel_ms, 90))},
         "step_hbm_frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "output_ring": {"buffers": RING, "MB": RING * ob / 1e6},
+        "one_output_buffer": one_buf,
         "ms_per_step_with_timing_events": ms_step_ev,
         "serial_steps": {"ms_per_step": ms_serial, "value": pts / (ms_serial * 1e-3)},
         "store_ceiling": {"kernel": "torch fill_ of the output buffer",
@@ -534,18 +574,21 @@ def main():
                       precision=prec)
         with torch.cuda.stream(stream):
             pp.forward_spectra(x, ws, stream=stream)
-            for _ in range(3):
-                pp.transform_spectra(C, out, ws, stream=stream)
+            for i in range(3):
+                pp.transform_spectra(C, ring[i * ob:(i + 1) * ob], ws, stream=stream)
             torch.cuda.synchronize()
             pp.timing_start(K)
-            for _ in range(K):
-                pp.transform_spectra(C, out, ws, stream=stream)
+            for i in range(K):
+                j = i % RING
+                pp.transform_spectra(C, ring[j * ob:(j + 1) * ob], ws, stream=stream)
             ms_p = float(np.mean(pp.timing_stop()))
         prec_runs.append({"precision": prec, "transform_ms": ms_p,
                           "transform_pts_per_s": pts / (ms_p * 1e-3),
                           "hbm_frac": transform_bytes / (ms_p * 1e-3) / 1e9 / HBM_PEAK_GBS})
         pp.close()
     result["precision_variants"] = prec_runs
+    del ring, fills
+    torch.cuda.empty_cache()
 
     if args.batch_steps > 0:
         result["batch"] = bench_batch(args.batch_steps)
