@@ -675,13 +675,14 @@ def test_generic_band_prologue(L, out):
     plan.close()
 
 
-@pytest.mark.parametrize("L", [1000, 4116])
+@pytest.mark.parametrize("L", [1000, 4116, 4096, 2048])
 def test_generic_band_prologue_sampled_wavelets(L):
-    """The prologue with complex spectra (plans from sampled wavelets).  A
-    float32 wavelet's rounding noise reaches every bin, so only wavelets with
-    exactly representable single-bin spectra have narrow bands: i^j (bin L/4)
-    and (-1)^j (bin L/2), one bin each, beside two Gaussian-windowed tones
-    whose bands cover the spectrum."""
+    """Narrow bands with complex spectra (plans from sampled wavelets): the
+    runtime-radix prologue (L 1000, 4116) and the register-resident band path
+    (L 4096, 2048).  A float32 wavelet's rounding noise reaches every bin, so
+    only wavelets with exactly representable single-bin spectra have narrow
+    bands: i^j (bin L/4) and (-1)^j (bin L/2), one bin each, beside two
+    Gaussian-windowed tones whose bands cover the spectrum."""
     sfreq = 1000.0
     N = L - 3
     j = np.arange(L)
@@ -692,11 +693,14 @@ def test_generic_band_prologue_sampled_wavelets(L):
     freqs = np.array([250.0, 499.0, 30.0, 90.0])
     x = synth.eeg(2, N, sfreq, 11)
     plan = cwt.Plan.from_wavelets(N, sfreq, freqs, wv, pad="explicit", explicit_len=L)
-    assert plan.L == L and plan.desc.kernel == 0 and plan.desc.spectrum_complex == 1
+    fixed = L in (2048, 4096)
+    assert plan.L == L and plan.desc.kernel == (1 if fixed else 0)
+    assert plan.desc.spectrum_complex == 1
     _, band, _ = plan.tables()
     p0 = [_skipped_passes(int(K), L, plan.radices) for K in band[:, 1]]
     print("sampled L=%d bands %s skipped passes %s" % (L, band[:, :2].tolist(), p0))
-    assert band[0, 1] == 1 and band[1, 1] == 1 and p0[0] == len(plan.radices) - 1
+    assert band[0, 1] == 1 and band[1, 1] == 1
+    assert fixed or p0[0] == len(plan.radices) - 1
     W = plan.execute(torch.from_numpy(x).cuda()).cpu().numpy()
     ref = oracle.cwt_user(x.astype(np.float64), wv.astype(np.complex64).astype(np.complex128),
                           pad="explicit", L=L)
