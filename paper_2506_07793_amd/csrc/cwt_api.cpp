@@ -631,6 +631,15 @@ int check_exec_args(const cwt_plan *P, const float *x, bool x_needed, int64_t C,
     const int64_t rows = (P->opts.out == CWT_OUT_BANDPOWER_F32) ? P->n_bands : P->F;
     if (C * rows > (int64_t)INT32_MAX)
         return fail(CWT_E_UNSUPPORTED, "C x rows exceeds the grid limit");
+    // one workgroup per output row; a launch holds fewer than 2^32 work-items
+    // (the forward-FFT workgroups of a pipelined launch included)
+    const int64_t threads = (P->opts.precision != CWT_PREC_FP32) ? 256
+                            : P->use_fixed                       ? P->L / 16
+                                                                 : P->rp.threads;
+    if ((C * rows + (C + 1) / 2) * threads >= ((int64_t)1 << 32))
+        return fail(CWT_E_UNSUPPORTED,
+                    "%lld channels x %lld rows x %lld threads exceed one launch; split C",
+                    (long long)C, (long long)rows, (long long)threads);
     return CWT_OK;
 }
 

@@ -550,8 +550,16 @@ static hipError_t launch_batch_rows_t(const MainParams *items, const BatchTask *
                                       int threads, size_t lds, hipStream_t s)
 {
     set_lds_limit((const void *)k_batch_rows<MAXV, MODE>, lds);
-    hipLaunchKernelGGL((k_batch_rows<MAXV, MODE>), dim3(n), dim3(threads), lds, s, items, rows);
-    return hipGetLastError();
+    // a launch holds fewer than 2^32 work-items: larger classes take several
+    const int chunk = (int)((((int64_t)1 << 32) - 1) / threads);
+    for (int off = 0; off < n; off += chunk) {
+        const int m = n - off < chunk ? n - off : chunk;
+        hipLaunchKernelGGL((k_batch_rows<MAXV, MODE>), dim3(m), dim3(threads), lds, s, items,
+                           rows + off);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_batch_rows(const MainParams *items, const BatchTask *rows, int n, int threads,

@@ -11,8 +11,8 @@
 // magnitude in [2^14, 2^15) (FP16 range; undone exactly after the MFMA); BF16
 // keeps FP32's exponent range and is not scaled.  Twiddles are applied in
 // FP32 on the VALU when a stage stores its outputs; the DFT constants and
-// twiddles are FP64 values rounded once (the plan's twiddle table).  The forward transform of the
-// channels is the FP32 path's.
+// twiddles are FP64 values rounded once (the plan's twiddle table).  The
+// forward transform of the channels is the FP32 path's.
 #include "cwt_internal.hpp"
 #include "fft_core.hpp"
 

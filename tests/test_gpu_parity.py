@@ -707,3 +707,24 @@ def test_generic_band_prologue_sampled_wavelets(L):
     for i in range(4):
         _parity(W[:, i], ref[:, i], "sampled generic band prologue L=%d row %d" % (L, i))
     plan.close()
+
+
+def test_launch_work_item_limit():
+    """One workgroup per output row: a call whose launch would hold 2^32
+    work-items or more is refused before any launch (here 4096 rows of
+    1024-thread workgroups per channel: 1024 channels and up), and the largest
+    channel count below the limit still runs."""
+    from paper_2506_07793_amd import _lib
+    L = 16384
+    freqs = synth.log_freqs(0.5, 400.0, 4096)
+    plan = cwt.Plan(L, 1000.0, freqs, n_cycles=7.0)
+    assert plan.L == L and plan.desc.kernel == 0 and plan.desc.threads == 1024
+    C = 1100
+    x = torch.zeros(C, L, device="cuda")
+    ws = plan.alloc_workspace(C)
+    with pytest.raises(_lib.CwtError) as e:
+        plan.forward_spectra(x, ws)
+    assert e.value.code == _lib.CWT_E_UNSUPPORTED and "split C" in str(e.value)
+    plan.forward_spectra(x[:1000], ws)  # 1000 x 4096 x 1024 < 2^32
+    torch.cuda.synchronize()
+    plan.close()
