@@ -201,7 +201,11 @@ size_t cwt_workspace_size(const cwt_plan *plan, int64_t C);
  * workspace of at least cwt_workspace_size(plan, C) bytes, 256-byte aligned.
  * x, out and ws must not overlap.  Asynchronous on `stream`; the plan may be
  * executed concurrently on several streams, each with its own ws and out.
- * C == 0 is a no-op.
+ * C == 0 is a no-op.  Errors: CWT_E_INVALID for NULL or misaligned pointers
+ * (x 4-byte, out 8-byte, ws 256-byte aligned), C outside [0, 2^24] or a
+ * workspace too small; CWT_E_UNSUPPORTED when one launch would hold 2^32
+ * work-items or more (one workgroup of cwt_plan_desc.threads per output row
+ * of each channel, at most 1024 threads): split the channels over calls.
  */
 int cwt_execute(const cwt_plan *plan, const float *x, int64_t C, void *out, void *ws,
                 size_t ws_bytes, void *stream);
@@ -225,8 +229,9 @@ int cwt_transform_spectra(const cwt_plan *plan, int64_t C, void *out, void *ws,
  * Copy the plan's tables to host memory for inspection (synchronises
  * `stream`).  H_host receives spectrum_bins floats (the stored bins of every
  * frequency, frequency after frequency), or 2 * spectrum_bins floats
- * (complex, interleaved) when cwt_plan_desc.spectrum_complex is 1; band_host receives 3 ints per
- * frequency (first signed bin, number of bins, offset into H_host); tw_host
+ * (complex, interleaved) when cwt_plan_desc.spectrum_complex is 1;
+ * band_host receives 3 ints per frequency (first signed bin, number of bins,
+ * offset into H_host); tw_host
  * receives 2*L floats (the twiddle table).  Any pointer may be NULL.
  */
 int cwt_plan_copy_tables(const cwt_plan *plan, float *H_host, int32_t *band_host,
