@@ -72,26 +72,63 @@ int64_t pad_length(int64_t n, int mode, int64_t explicit_len)
     }
 }
 
+// Composite radices the passes implement (small factors sharing one pass).
+static bool composite_radix(int r)
+{
+    return r == 6 || r == 9 || r == 10 || r == 12 || r == 14 || r == 15;
+}
+
+// Fewest factors reachable from f by merging pairs into composite radices of
+// at most maxv whose pass still fits a 1024-thread workgroup (L / R
+// butterflies, maxv / R per thread); exhaustive over the few factors a
+// length has.
+static void merge_factors(std::vector<int> &f, int maxv, int L)
+{
+    std::vector<int> best = f;
+    for (size_t i = 0; i < f.size(); ++i)
+        for (size_t j = i + 1; j < f.size(); ++j) {
+            const int pr = f[i] * f[j];
+            if (!composite_radix(pr) || pr > maxv || L / pr > 1024 * (maxv / pr)) continue;
+            std::vector<int> g;
+            for (size_t k = 0; k < f.size(); ++k)
+                if (k != i && k != j) g.push_back(f[k]);
+            g.push_back(pr);
+            merge_factors(g, maxv, L);
+            if (g.size() < best.size()) best = g;
+        }
+    f = best;
+}
+
 // Radix schedule: the largest radices first (16, 8, 4, 2, then 7, 5, 3),
 // falling back to schedules without 16 (then without 8) when a thread of a
-// 1024-wide workgroup would have to hold too many values.  The workgroup size
-// is the smallest multiple of 64 (at least L/16) for which no thread holds
-// more than maxv values in any pass; maxv is 16 when possible, else 24.
-static bool try_radix_plan(int L, const int *order, int n_order, int maxv, RadixPlan &rp)
+// 1024-wide workgroup would have to hold too many values; with `merge`, small
+// factors are paired into composite radices (2x3, 3x3, 2x5, 4x3, 2x7, 3x5)
+// wherever that saves passes, and the passes run largest radix first.  The
+// workgroup size is the smallest multiple of 64 (at least L/16) for which no
+// thread holds more than maxv values in any pass; maxv is 16 when possible,
+// else 24.
+static bool try_radix_plan(int L, const int *order, int n_order, int maxv, bool merge,
+                           RadixPlan &rp)
 {
     rp = RadixPlan{};
     rp.L = L;
     int m = L;
-    int np = 0;
+    std::vector<int> f;
     for (int oi = 0; oi < n_order; ++oi) {
         const int r = order[oi];
         while (m % r == 0) {
-            if (np >= kMaxPasses) return false;
-            rp.radix[np++] = r;
+            f.push_back(r);
             m /= r;
         }
     }
     if (m != 1) return false;
+    if (merge && f.size() > 1) {
+        merge_factors(f, maxv, L);
+        std::stable_sort(f.begin(), f.end(), [](int a, int b) { return a > b; });
+    }
+    if ((int)f.size() > kMaxPasses) return false;
+    int np = 0;
+    for (int r : f) rp.radix[np++] = r;
     if (np == 0) rp.radix[np++] = 1;  // L == 1: a single identity pass
     rp.n_pass = np;
     for (int T = std::max(64, std::min(1024, ((L / 16 + 63) / 64) * 64)); T <= 1024; T += 64) {
@@ -121,21 +158,22 @@ void radix_candidates(int L, std::vector<RadixPlan> &out)
     const int lens[] = {7, 6, 5};
     out.clear();
     for (int maxv : {16, 24})
-        for (int o = 0; o < 3; ++o) {
-            RadixPlan rp;
-            if (!try_radix_plan(L, orders[o], lens[o], maxv, rp)) continue;
-            for (int mul = 1; mul <= 2; ++mul) {
-                RadixPlan c = rp;
-                c.threads = rp.threads * mul;
-                if (c.threads > 1024) continue;
-                bool dup = false;
-                for (const RadixPlan &q : out)
-                    if (q.threads == c.threads && q.maxv == c.maxv && q.n_pass == c.n_pass &&
-                        std::equal(q.radix, q.radix + q.n_pass, c.radix))
-                        dup = true;
-                if (!dup) out.push_back(c);
+        for (bool merge : {true, false})
+            for (int o = 0; o < 3; ++o) {
+                RadixPlan rp;
+                if (!try_radix_plan(L, orders[o], lens[o], maxv, merge, rp)) continue;
+                for (int mul = 1; mul <= 2; ++mul) {
+                    RadixPlan c = rp;
+                    c.threads = rp.threads * mul;
+                    if (c.threads > 1024) continue;
+                    bool dup = false;
+                    for (const RadixPlan &q : out)
+                        if (q.threads == c.threads && q.maxv == c.maxv && q.n_pass == c.n_pass &&
+                            std::equal(q.radix, q.radix + q.n_pass, c.radix))
+                            dup = true;
+                    if (!dup) out.push_back(c);
+                }
             }
-        }
 }
 
 bool make_radix_plan(int L, RadixPlan &rp)
@@ -143,11 +181,12 @@ bool make_radix_plan(int L, RadixPlan &rp)
     static const int o1[] = {16, 8, 4, 2, 7, 5, 3};
     static const int o2[] = {8, 4, 2, 7, 5, 3};
     static const int o3[] = {4, 2, 7, 5, 3};
-    for (int maxv : {16, 24}) {
-        if (try_radix_plan(L, o1, 7, maxv, rp)) return true;
-        if (try_radix_plan(L, o2, 6, maxv, rp)) return true;
-        if (try_radix_plan(L, o3, 5, maxv, rp)) return true;
-    }
+    for (int maxv : {16, 24})
+        for (bool merge : {true, false}) {
+            if (try_radix_plan(L, o1, 7, maxv, merge, rp)) return true;
+            if (try_radix_plan(L, o2, 6, maxv, merge, rp)) return true;
+            if (try_radix_plan(L, o3, 5, maxv, merge, rp)) return true;
+        }
     return false;
 }
 

@@ -285,6 +285,24 @@ __device__ __forceinline__ void band_prologue_rt(int R0, bool sw, gptr<cf> X, gp
         if (sw) band_prologue<2, true>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
         else band_prologue<2, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
         break;
+    case 12:
+        if (sw) band_prologue<12, true>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        else band_prologue<12, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        break;
+    case 14:
+        if (sw) band_prologue<14, true>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        else band_prologue<14, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        break;
+    case 10:
+        if (sw) band_prologue<10, true>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        else band_prologue<10, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        break;
+    case 6:
+        if (sw) band_prologue<6, true>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        else band_prologue<6, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        break;
+    case 15: band_prologue<15, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw); break;
+    case 9: band_prologue<9, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw); break;
     case 7: band_prologue<7, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw); break;
     case 5: band_prologue<5, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw); break;
     case 3: band_prologue<3, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw); break;

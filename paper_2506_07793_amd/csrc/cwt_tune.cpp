@@ -2,6 +2,7 @@
 // keeps the fastest; optional cache file keyed by (device, L, output, precision).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -81,11 +82,22 @@ void apply_tuning_cache(cwt_plan &P)
             int r, used = 0;
             if (std::sscanf(q, "%d%n", &r, &used) != 1) ok = 0;
             q += used;
+            // radices the passes implement
+            if (ok && !(r == 1 || r == 2 || r == 3 || r == 4 || r == 5 || r == 6 || r == 7 ||
+                        r == 8 || r == 9 || r == 10 || r == 12 || r == 14 || r == 15 || r == 16))
+                ok = 0;
+            if (!ok) break;
             rp.radix[i] = r;
             prod *= r;
         }
         if (!ok || prod != L || threads < 64 || threads > 1024 || (maxv != 16 && maxv != 24))
             continue;
+        // every pass's butterflies fit the workgroup (as the planner requires)
+        for (int i = 0; i < n && ok; ++i) {
+            const int S = L / rp.radix[i];
+            if ((S + threads - 1) / threads > std::max(1, maxv / rp.radix[i])) ok = 0;
+        }
+        if (!ok) continue;
         if (kernel == 1 && !fixed_main_available(L)) continue;
         best = Config{kernel == 1, variant, rp};
         found = true;  // the last matching line wins

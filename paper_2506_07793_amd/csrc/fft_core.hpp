@@ -234,6 +234,60 @@ struct Dft<5, SIGN> : DftOdd<5, SIGN> {};
 template <int SIGN>
 struct Dft<7, SIGN> : DftOdd<7, SIGN> {};
 
+// Composite radices R = R1 R2 (small factors merged into one pass, so that a
+// length does not spend an LDS round trip and two barriers on a radix-2 or
+// radix-3 pass): with r = R2 r1 + r2 and k = k1 + R1 k2,
+//   V[k] = sum_r2 W_R2^(r2 k2) [ W_R^(r2 k1) sum_r1 v[R2 r1 + r2] W_R1^(r1 k1) ],
+// W_M = exp(SIGN 2 pi i / M); wn[m] = W_R^m (table values, rounded once).
+template <int R>
+struct CompSplit {
+    static constexpr int r1 = 0, r2 = 0;  // not composite
+};
+template <> struct CompSplit<6> { static constexpr int r1 = 2, r2 = 3; };
+template <> struct CompSplit<9> { static constexpr int r1 = 3, r2 = 3; };
+template <> struct CompSplit<10> { static constexpr int r1 = 2, r2 = 5; };
+template <> struct CompSplit<12> { static constexpr int r1 = 4, r2 = 3; };
+template <> struct CompSplit<14> { static constexpr int r1 = 2, r2 = 7; };
+template <> struct CompSplit<15> { static constexpr int r1 = 3, r2 = 5; };
+
+template <int R1, int R2, int SIGN>
+struct DftC {
+    static __device__ __forceinline__ void run(cf *v, const cf *wn)
+    {
+        constexpr int R = R1 * R2;
+        cf a[R2][R1];
+#pragma unroll
+        for (int r2 = 0; r2 < R2; ++r2) {
+            cf t[R1];
+#pragma unroll
+            for (int r1 = 0; r1 < R1; ++r1) t[r1] = v[R2 * r1 + r2];
+            Dft<R1, SIGN>::run(t);
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1)
+                a[r2][k1] = (r2 * k1 == 0) ? t[k1] : mul(t[k1], wn[(r2 * k1) % R]);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            cf t[R2];
+#pragma unroll
+            for (int r2 = 0; r2 < R2; ++r2) t[r2] = a[r2][k1];
+            Dft<R2, SIGN>::run(t);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = t[k2];
+        }
+    }
+};
+
+// The R-point transform of one butterfly, plain or composite.
+template <int R, int SIGN>
+__device__ __forceinline__ void codelet(cf *v, const cf *wn)
+{
+    if constexpr (CompSplit<R>::r1 > 0)
+        DftC<CompSplit<R>::r1, CompSplit<R>::r2, SIGN>::run(v, wn);
+    else
+        Dft<R, SIGN>::run(v);
+}
+
 // LDS slot of element i in the buffer between the first and the second pass
 // of a plan whose first radix is even: the low four bits are XORed with bits
 // 4-7, so that the first pass's scatter to R j + r (R even) reaches 16
@@ -286,6 +340,12 @@ __device__ __attribute__((noinline)) void stockham_pass(int L, int Ns, int T, in
         }
     }
     if (SYNC_MID) __syncthreads();
+    // internal twiddles of a composite radix: W_R^m = tw[m L / R]
+    cf wn[CompSplit<R>::r1 > 0 ? R : 1];
+    if constexpr (CompSplit<R>::r1 > 0) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) wn[m] = conj_if<SIGN>(load_cf(tw + m * (L / R)));
+    }
     // jm = j mod Ns for j = tid + k T, stepped by T mod Ns (one division per
     // pass instead of one per butterfly)
     const int dT = T % Ns;
@@ -304,7 +364,7 @@ __device__ __attribute__((noinline)) void stockham_pass(int L, int Ns, int T, in
 #pragma unroll
                 for (int r = 1; r < R; ++r) v[k][r] = mul(v[k][r], w[r]);
             }
-            Dft<R, SIGN>::run(v[k]);
+            codelet<R, SIGN>(v[k], wn);
             const int base = (j - jm) * R + jm;
 #pragma unroll
             for (int r = 0; r < R; ++r) store(k * R + r, base + r * Ns, v[k][r]);
@@ -325,6 +385,12 @@ __device__ __forceinline__ void stockham_pass_rt(int R, int L, int Ns, int T, in
     case 3: stockham_pass<3, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
     case 5: stockham_pass<5, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
     case 7: stockham_pass<7, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
+    case 6: stockham_pass<6, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
+    case 9: stockham_pass<9, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
+    case 10: stockham_pass<10, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
+    case 12: stockham_pass<12, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
+    case 14: stockham_pass<14, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
+    case 15: stockham_pass<15, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
     case 1: stockham_pass<1, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
     default: break;
     }

@@ -68,11 +68,27 @@ def test_padded_length_and_radices(n, pad, expl, L):
     assert d.L == L
     radix = [d.radix[i] for i in range(d.n_passes)]
     assert int(np.prod(radix)) == L
-    assert all(r in (1, 2, 3, 4, 5, 7, 8, 16) for r in radix)
+    # the radices the passes implement: primes and powers of two, and the
+    # composites 2x3, 3x3, 2x5, 4x3, 2x7, 3x5 that merge small factors
+    assert all(r in (1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 14, 15, 16) for r in radix)
     # no thread holds more values than the kernel's register budget
     for r in radix:
         nb = -(-(L // r) // d.threads)
         assert nb <= max(1, 24 // r)
+        assert r <= 16
+
+
+@pytest.mark.parametrize("L,radix", [
+    (4116, [12, 7, 7, 7]), (2187, [9, 9, 9, 3]), (1680, [16, 15, 7]), (105, [15, 7]),
+    (98, [14, 7]), (3072, [16, 16, 12]), (1000, [8, 5, 5, 5]), (10000, [16, 5, 5, 5, 5]),
+    (4096, [16, 16, 16]),
+])
+def test_composite_radices_save_passes(L, radix):
+    """Small leftover factors share a pass (fewest passes; largest radix
+    first), and lengths without such factors keep their schedule."""
+    d = cwt.describe(L, 1000.0, np.array([10.0, 20.0]), n_cycles=7.0, pad="explicit",
+                     explicit_len=L)
+    assert [d.radix[i] for i in range(d.n_passes)] == radix
 
 
 def test_planner_matches_oracle_padding():
