@@ -240,6 +240,56 @@ int enqueue_kernels(const std::vector<ClassInfo> &classes, char *ws, const Layou
     return CWT_OK;
 }
 
+// One item as its own pair of launches (the default form).
+struct ItemLaunch {
+    int item;
+    int fwd_blocks, main_blocks, threads, maxv, mode;
+    size_t lds;
+    double cost;
+};
+
+// Items longest first, each assigned to the least loaded of up to four
+// branches (the process's hardware queues); each branch runs its items'
+// forward and transform launches in order.
+int enqueue_items(const std::vector<ItemLaunch> &its, char *ws, const Layout &Lo, hipStream_t s)
+{
+    const int nb = (int)std::min<size_t>(4, its.size());
+    const bool fork = nb > 1;
+    Fork *fk = nullptr;
+    hipError_t e;
+    if (fork) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        int rc = get_fork(dev, nb, fk);
+        if (rc != CWT_OK) return rc;
+        e = hipEventRecord(fk->fork, s);
+        if (e != hipSuccess) return hip_fail(e, "batch fork");
+        for (int b = 0; b < nb; ++b) {
+            e = hipStreamWaitEvent(fk->side[b], fk->fork, 0);
+            if (e != hipSuccess) return hip_fail(e, "batch fork wait");
+        }
+    }
+    std::vector<double> load(nb, 0.0);
+    const FwdParams *fi = reinterpret_cast<const FwdParams *>(ws + Lo.fwd_items);
+    const MainParams *mi = reinterpret_cast<const MainParams *>(ws + Lo.main_items);
+    for (const ItemLaunch &it : its) {
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[b] += it.cost;
+        hipStream_t sb = fork ? fk->side[b] : s;
+        e = launch_item_forward(fi, it.item, it.fwd_blocks, it.threads, it.maxv, it.lds, sb);
+        if (e != hipSuccess) return hip_fail(e, "batch item forward launch");
+        e = launch_item_main(mi, it.item, it.main_blocks, it.threads, it.maxv, it.mode, it.lds, sb);
+        if (e != hipSuccess) return hip_fail(e, "batch item transform launch");
+    }
+    if (fork)
+        for (int b = 0; b < nb; ++b) {
+            e = hipEventRecord(fk->join[b], fk->side[b]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, fk->join[b], 0);
+            if (e != hipSuccess) return hip_fail(e, "batch join");
+        }
+    return CWT_OK;
+}
+
 }  // namespace
 
 extern "C" size_t cwt_batch_workspace_size(const cwt_batch_item *items, int32_t n)
@@ -266,10 +316,15 @@ extern "C" int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *w
     if (((uintptr_t)ws & 255) != 0) return fail(CWT_E_INVALID, "ws must be 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
 
+    // Form: one launch pair per item (default), or the persistent class
+    // kernels (CWT_BATCH_KERNELS=persistent), which alone need task lists.
+    const char *km = std::getenv("CWT_BATCH_KERNELS");
+    const bool persistent = km && std::strcmp(km, "persistent") == 0;
+
     // Tasks, grouped by workgroup-size class (and output mode for the
     // one-row-per-workgroup classes).
     std::map<std::tuple<int, int, int>, ClassInfo> by_class;
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < n && persistent; ++i) {
         const cwt_plan &P = *items[i].plan;
         if (items[i].C == 0) continue;
         const int thr = class_threads(P.rp.threads);
@@ -406,6 +461,33 @@ extern "C" int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *w
         shape.insert(shape.end(), {c.threads, c.maxv, c.max_L, c.mode, (int64_t)c.fwd.size(),
                                    (int64_t)c.main.size()});
     }
+    std::vector<ItemLaunch> its;
+    if (!persistent) {
+        for (int i = 0; i < n; ++i) {
+            const cwt_plan &P = *items[i].plan;
+            if (items[i].C == 0) continue;
+            const int64_t rows = (P.opts.out == CWT_OUT_BANDPOWER_F32) ? P.n_bands : P.F;
+            ItemLaunch it;
+            it.item = i;
+            it.fwd_blocks = (int)((items[i].C + 1) / 2);
+            it.main_blocks = (int)(items[i].C * rows);
+            it.threads = P.rp.threads;
+            it.maxv = P.rp.maxv;
+            it.mode = (int)P.opts.out;
+            it.lds = generic_lds_bytes(P.L);
+            it.cost = (double)items[i].C * rows * row_cost(P);
+            if ((int64_t)it.main_blocks * it.threads >= ((int64_t)1 << 32))
+                return fail(CWT_E_UNSUPPORTED,
+                            "items[%d]: C x rows x threads reaches 2^32 work-items; split C", i);
+            its.push_back(it);
+        }
+        std::stable_sort(its.begin(), its.end(),
+                         [](const ItemLaunch &a, const ItemLaunch &b) { return a.cost > b.cost; });
+        shape.push_back(-1);
+        for (const ItemLaunch &it : its)
+            shape.insert(shape.end(), {it.item, it.fwd_blocks, it.main_blocks, it.threads,
+                                       it.maxv, it.mode, (int64_t)it.lds});
+    }
     shape.insert(shape.end(), {(int64_t)Lo.total, n});
     e = hipMemcpyAsync(dws + Lo.fwd_items, h + Lo.fwd_items, table_bytes - Lo.fwd_items,
                        hipMemcpyHostToDevice, s);
@@ -416,7 +498,10 @@ extern "C" int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *w
     // Launch: replay the cached graph, or capture one.
     const char *g = std::getenv("CWT_BATCH_GRAPH");
     const bool use_graph = !(g && g[0] == '0');
-    if (!use_graph) return enqueue_kernels(classes, dws, Lo, s);
+    auto enqueue = [&](hipStream_t q) {
+        return persistent ? enqueue_kernels(classes, dws, Lo, q) : enqueue_items(its, dws, Lo, q);
+    };
+    if (!use_graph) return enqueue(s);
     GraphCache &gc = cache();
     std::lock_guard<std::mutex> glk(gc.mu);
     GraphKey key{ws, dev, shape};
@@ -429,7 +514,7 @@ extern "C" int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *w
         }
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        rc = enqueue_kernels(classes, dws, Lo, cs);
+        rc = enqueue(cs);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(cs, &graph);
         if (rc != CWT_OK) {

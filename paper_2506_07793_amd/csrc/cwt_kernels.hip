@@ -111,8 +111,8 @@ hipError_t launch_user_spectra(const float2 *w, int F, int wl, int c, int L, dou
 // --------------------------------------------------------- forward FFT --
 
 // Forward transform of channel pair `pair` (channels 2 pair, 2 pair + 1).
-template <int MAXV>
-__device__ __forceinline__ void forward_task(const FwdParams &p, int pair)
+template <int MAXV, class P = FwdParams>
+__device__ __forceinline__ void forward_task(const P &p, int pair)
 {
     extern __shared__ cf lds[];
     const int L = p.rp.L, T = blockDim.x, tid = threadIdx.x;
@@ -503,6 +503,28 @@ __global__ void __launch_bounds__(1024)
     main_task<MAXV, MODE>(p, (int)tk.a, (int)tk.b);
 }
 
+// One item of a batch as its own launch (grid: the item's channel pairs or
+// output rows), its parameters read from the batch's table through the
+// constant address space: a captured graph of these launches stays valid for
+// any later call with the same layout, as the table is uploaded per call.
+template <int MAXV>
+__global__ void __launch_bounds__(1024) k_item_forward(const FwdParams *items, int item)
+{
+    typedef const __attribute__((address_space(4))) FwdParams CFP;
+    CFP &p = *(CFP *)(items + item);
+    forward_task<MAXV>(p, blockIdx.x);
+}
+
+template <int MAXV, int MODE>
+__global__ void __launch_bounds__(1024) k_item_main(const MainParams *items, int item)
+{
+    typedef const __attribute__((address_space(4))) MainParams CMP;
+    CMP &p = *(CMP *)(items + item);
+    const int n_rows = p.n_rows;
+    const int c = blockIdx.x / n_rows;
+    main_task<MAXV, MODE>(p, c, (int)blockIdx.x - c * n_rows);
+}
+
 __global__ void k_zero_counters(int *c, int n)
 {
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
@@ -595,6 +617,48 @@ hipError_t launch_batch_rows(const MainParams *items, const BatchTask *rows, int
     case kOutComplex: return launch_batch_rows_t<24, kOutComplex>(items, rows, n, threads, lds, s);
     case kOutPower: return launch_batch_rows_t<24, kOutPower>(items, rows, n, threads, lds, s);
     default: return launch_batch_rows_t<24, kOutBand>(items, rows, n, threads, lds, s);
+    }
+}
+
+hipError_t launch_item_forward(const FwdParams *items, int item, int blocks, int threads,
+                               int maxv, size_t lds, hipStream_t s)
+{
+    if (blocks == 0) return hipSuccess;
+    if (maxv <= 16) {
+        set_lds_limit((const void *)k_item_forward<16>, lds);
+        hipLaunchKernelGGL(k_item_forward<16>, dim3(blocks), dim3(threads), lds, s, items, item);
+    } else {
+        set_lds_limit((const void *)k_item_forward<24>, lds);
+        hipLaunchKernelGGL(k_item_forward<24>, dim3(blocks), dim3(threads), lds, s, items, item);
+    }
+    return hipGetLastError();
+}
+
+template <int MAXV, int MODE>
+static hipError_t launch_item_main_t(const MainParams *items, int item, int blocks, int threads,
+                                     size_t lds, hipStream_t s)
+{
+    set_lds_limit((const void *)k_item_main<MAXV, MODE>, lds);
+    hipLaunchKernelGGL((k_item_main<MAXV, MODE>), dim3(blocks), dim3(threads), lds, s, items,
+                       item);
+    return hipGetLastError();
+}
+
+hipError_t launch_item_main(const MainParams *items, int item, int blocks, int threads, int maxv,
+                            int mode, size_t lds, hipStream_t s)
+{
+    if (blocks == 0) return hipSuccess;
+    if (maxv <= 16) {
+        switch (mode) {
+        case kOutComplex: return launch_item_main_t<16, kOutComplex>(items, item, blocks, threads, lds, s);
+        case kOutPower: return launch_item_main_t<16, kOutPower>(items, item, blocks, threads, lds, s);
+        default: return launch_item_main_t<16, kOutBand>(items, item, blocks, threads, lds, s);
+        }
+    }
+    switch (mode) {
+    case kOutComplex: return launch_item_main_t<24, kOutComplex>(items, item, blocks, threads, lds, s);
+    case kOutPower: return launch_item_main_t<24, kOutPower>(items, item, blocks, threads, lds, s);
+    default: return launch_item_main_t<24, kOutBand>(items, item, blocks, threads, lds, s);
     }
 }
 

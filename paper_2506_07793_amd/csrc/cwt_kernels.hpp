@@ -77,6 +77,12 @@ hipError_t launch_batch_main(const MainParams *items, const BatchTask *tasks, in
 // output mode; n workgroups.
 hipError_t launch_batch_rows(const MainParams *items, const BatchTask *rows, int n, int threads,
                              int maxv, int mode, size_t lds, hipStream_t s);
+// One batch item as its own launch, parameters read from the device table:
+// `blocks` channel pairs (forward) or channels x rows (transform).
+hipError_t launch_item_forward(const FwdParams *items, int item, int blocks, int threads,
+                               int maxv, size_t lds, hipStream_t s);
+hipError_t launch_item_main(const MainParams *items, int item, int blocks, int threads, int maxv,
+                            int mode, size_t lds, hipStream_t s);
 
 // ----------------------------------------------------------- streaming --
 // One completed hop of one session.

@@ -1,5 +1,6 @@
-"""Batched form on the GPU: heterogeneous recordings in one graph launch of
-persistent kernels, checked against the FP64 oracle and against cwt_execute."""
+"""Batched form on the GPU: heterogeneous recordings in one graph launch (one
+launch pair per recording by default, or persistent class kernels), checked
+against the FP64 oracle and against cwt_execute."""
 import numpy as np
 import pytest
 import torch
@@ -56,9 +57,11 @@ SPECS = [(1000, 3, 20, 250.0, "complex64"), (4116, 2, 33, 1000.0, "power"),
          (19999, 1, 20, 2048.0, "complex64")]
 
 
+@pytest.mark.parametrize("kernels", ["items", "persistent"])
 @pytest.mark.parametrize("graph", ["1", "0"])
-def test_heterogeneous_batch_matches_oracle(graph, monkeypatch):
+def test_heterogeneous_batch_matches_oracle(graph, kernels, monkeypatch):
     monkeypatch.setenv("CWT_BATCH_GRAPH", graph)
+    monkeypatch.setenv("CWT_BATCH_KERNELS", kernels)
     its = _items(SPECS, seed=30)
     b = cwt.Batch([(it["plan"], it["xt"], it["out"]) for it in its])
     ws = b.alloc_workspace()
