@@ -122,6 +122,34 @@ def test_eeg_full_size_sampled_rows():
     plan.close()
 
 
+def test_eeg_full_size_pipelined_batches():
+    """The benchmarked launch form: cwt_execute_batches over three distinct
+    64 ch x 4096 x 100-freq batches (each launch the transform of one batch
+    and the forward FFT of the next), oracle on sampled rows of every batch,
+    and the middle batch equal bit for bit to a plain cwt_execute."""
+    nb, C = 3, 64
+    ds = [synth.eeg_64ch(seed=20 + i) for i in range(nb)]
+    sfreq, freqs, cyc = ds[0]["sfreq"], ds[0]["freqs"], ds[0]["n_cycles"]
+    xs = np.stack([d["x"] for d in ds]).astype(np.float32)
+    plan = cwt.Plan(4096, sfreq, freqs, n_cycles=cyc)
+    assert plan.desc.kernel == 1
+    x = torch.from_numpy(xs).cuda()
+    out = torch.empty((nb,) + tuple(plan.output_shape(C)), dtype=torch.complex64, device="cuda")
+    ws = plan.alloc_batches_workspace(C)
+    plan.execute_batches(x, nb, out, ws, C)
+    single = plan.execute(x[1])
+    torch.cuda.synchronize()
+    assert torch.equal(out[1], single)
+    rng = np.random.default_rng(12)
+    for i in range(nb):
+        rows = np.stack([rng.integers(0, C, 6), rng.integers(0, 100, 6)], axis=1)
+        rows[0] = (i, 99 - i)
+        ref = oracle.cwt(xs[i].astype(np.float64), sfreq, freqs, cyc, rows=rows)
+        got = out[i][torch.from_numpy(rows[:, 0]).cuda(), torch.from_numpy(rows[:, 1]).cuda()]
+        _parity(got.cpu().numpy(), ref, "pipelined batch %d sampled" % i)
+    plan.close()
+
+
 def test_eeg_power_and_bandpower():
     x, sfreq, freqs, cyc = _eeg(3)
     ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc)
