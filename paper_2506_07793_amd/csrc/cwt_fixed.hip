@@ -2,10 +2,10 @@
 //
 // Each workgroup of T = L/16 threads transforms one length-L sequence; every
 // thread holds 16 complex values in registers and the radix passes exchange
-// data through LDS.  LDS slots are XOR-swizzled (low five index bits XORed
-// with a function of the higher bits) so that the strided writes of the first
-// passes and the unit-stride reads both hit 32 distinct 8-byte slots per 32
-// lanes.  Twiddles are read from the plan's exp(2 pi i m / L) table.  The
+// data through LDS.  LDS slots are XOR-swizzled (the low four index bits
+// XORed with higher bits) so that neither the strided writes of the first
+// passes nor the unit-stride reads meet bank conflicts (see sw() below for
+// the gfx950 rule).  Twiddles come from the plan's exp(2 pi i m / L) table.  The
 // radix schedule is a compile-time list whose first entry is 16, so every
 // pass is fully unrolled with constant strides.
 //
@@ -435,12 +435,13 @@ static hipError_t launch_fixed_forward_t(const FwdParams &p, hipStream_t s)
 {
     constexpr int L = RList<Rs...>::product;
     const size_t lds = (size_t)L * sizeof(cf);
-    static bool attr_set = false;
-    if (!attr_set) {
+    // once per process (thread-safe static initialisation)
+    static const bool attr_set = [lds] {
         (void)hipFuncSetAttribute((const void *)k_fixed_forward<Rs...>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr_set = true;
-    }
+        return true;
+    }();
+    (void)attr_set;
     hipLaunchKernelGGL((k_fixed_forward<Rs...>), dim3((p.C + 1) / 2), dim3(L / kV), lds, s, p);
     return hipGetLastError();
 }
@@ -461,12 +462,13 @@ static hipError_t launch_fixed_t(const MainParams &p, hipStream_t s, LaunchEvent
 {
     constexpr int L = RList<Rs...>::product;
     const size_t lds = (size_t)L * sizeof(cf);
-    static bool attr_set = false;
-    if (!attr_set) {
+    // once per process (thread-safe static initialisation)
+    static const bool attr_set = [lds] {
         (void)hipFuncSetAttribute((const void *)k_fixed_main<MODE, TWM, Rs...>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr_set = true;
-    }
+        return true;
+    }();
+    (void)attr_set;
     hipExtLaunchKernelGGL((k_fixed_main<MODE, TWM, Rs...>), dim3(p.C * p.n_rows), dim3(L / kV),
                           lds, s, ev.start, ev.stop, 0, p);
     return hipGetLastError();
@@ -495,12 +497,13 @@ static hipError_t launch_fused_t(const MainParams &p, const FwdParams &f, hipStr
 {
     constexpr int L = RList<Rs...>::product;
     const size_t lds = (size_t)L * sizeof(cf);
-    static bool attr_set = false;
-    if (!attr_set) {
+    // once per process (thread-safe static initialisation)
+    static const bool attr_set = [lds] {
         (void)hipFuncSetAttribute((const void *)k_fixed_fused<MODE, TWM, Rs...>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr_set = true;
-    }
+        return true;
+    }();
+    (void)attr_set;
     const int n_fwd = (f.C + 1) / 2;
     hipExtLaunchKernelGGL((k_fixed_fused<MODE, TWM, Rs...>), dim3(n_fwd + p.C * p.n_rows),
                           dim3(L / kV), lds, s, ev.start, ev.stop, 0, p, f, n_fwd);
