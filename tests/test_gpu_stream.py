@@ -165,3 +165,39 @@ def test_open_rejects_bad_arguments():
     srv.close()
     plan_c.close()
     plan_b.close()
+
+
+def test_serving_full_size_512_sessions():
+    """The benchmarked serving shape: 512 sessions of 64 channels at 1000 Hz
+    (2 s window, 50 ms hop, 40 frequencies 1-100 Hz, band power), hops pushed
+    interleaved across sessions.  Every session yields exactly its three
+    full-window results in hop order, all finite and non-negative; four
+    channels of the last window of three sessions are checked against the
+    oracle."""
+    W, hop, sfreq, C, n_s = 2000, 50, 1000.0, 64, 512
+    plan, freqs, cyc = _plan(W, sfreq, 40, 100.0)
+    srv = Server(8 << 30, max_batch=512, deadline_us=1000)
+    sess = [srv.open(plan, C, hop) for _ in range(n_s)]
+    T = W + 2 * hop
+    xs = [synth.eeg(C, T, sfreq, seed=1000 + i) for i in range(n_s)]
+    for k in range(0, T, hop):
+        for s, x in zip(sess, xs):
+            assert s.push(x[:, k:k + hop])
+    srv.flush()
+    for i, (s, x) in enumerate(zip(sess, xs)):
+        res = []
+        while True:
+            r = s.poll()
+            if r is None:
+                break
+            res.append((r[0], r[1]))
+        assert [h for _, h in res] == [T // hop - 3, T // hop - 2, T // hop - 1], i
+        for bp, _ in res:
+            assert np.all(np.isfinite(bp)) and float(bp.min()) >= 0.0
+        if i in (0, 255, 511):
+            bp, h = res[-1]
+            _check([(bp[:4], h)], x[:4], W, hop, sfreq, freqs, cyc, "session %d" % i)
+    st = srv.stats()
+    assert st["results"] == 3 * n_s and st["hops"] == n_s * (T // hop)
+    srv.close()
+    plan.close()
