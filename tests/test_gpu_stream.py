@@ -167,18 +167,19 @@ def test_open_rejects_bad_arguments():
     plan_b.close()
 
 
-def test_serving_full_size_512_sessions():
-    """The benchmarked serving shape: 512 sessions of 64 channels at 1000 Hz
-    (2 s window, 50 ms hop, 40 frequencies 1-100 Hz, band power), hops pushed
-    interleaved across sessions.  Every session yields exactly its three
-    full-window results in hop order, all finite and non-negative; four
-    channels of the last window of three sessions are checked against the
-    oracle."""
-    W, hop, sfreq, C, n_s = 2000, 50, 1000.0, 64, 512
+@pytest.mark.parametrize("n_s,C,sfreq,W,hop", [(512, 64, 1000.0, 2000, 50), (64, 256, 2048.0, 4096, 102)])
+def test_serving_full_size(n_s, C, sfreq, W, hop):
+    """The benchmarked serving shapes: 512 sessions of 64 channels at 1000 Hz
+    and 64 sessions of 256 channels at 2048 Hz (2 s window, 50 ms hop, 40
+    frequencies 1-100 Hz, band power), hops pushed interleaved across
+    sessions.  Every session yields exactly its full-window results in hop
+    order, all finite and non-negative; four channels of the last window of
+    three sessions are checked against the oracle."""
     plan, freqs, cyc = _plan(W, sfreq, 40, 100.0)
     srv = Server(8 << 30, max_batch=512, deadline_us=1000)
     sess = [srv.open(plan, C, hop) for _ in range(n_s)]
     T = W + 2 * hop
+    expect = [h for h in range(T // hop) if (h + 1) * hop >= W]  # full-window hops
     xs = [synth.eeg(C, T, sfreq, seed=1000 + i) for i in range(n_s)]
     for k in range(0, T, hop):
         for s, x in zip(sess, xs):
@@ -191,13 +192,13 @@ def test_serving_full_size_512_sessions():
             if r is None:
                 break
             res.append((r[0], r[1]))
-        assert [h for _, h in res] == [T // hop - 3, T // hop - 2, T // hop - 1], i
+        assert [h for _, h in res] == expect, i
         for bp, _ in res:
             assert np.all(np.isfinite(bp)) and float(bp.min()) >= 0.0
-        if i in (0, 255, 511):
+        if i in (0, n_s // 2 - 1, n_s - 1):
             bp, h = res[-1]
             _check([(bp[:4], h)], x[:4], W, hop, sfreq, freqs, cyc, "session %d" % i)
     st = srv.stats()
-    assert st["results"] == 3 * n_s and st["hops"] == n_s * (T // hop)
+    assert st["results"] == len(expect) * n_s and st["hops"] == n_s * (T // hop)
     srv.close()
     plan.close()
