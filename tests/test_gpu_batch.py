@@ -135,19 +135,21 @@ def test_full_recording_draw_one_graph():
     """The benchmarked batch at its full size: all 256 recordings of the seeded
     draw (lengths 500-20000, their full 1-128 channels, power out) in one graph
     launch of the default form.  Every output is finite and non-negative; one
-    row of every eighth recording (a channel of structured synthetic EEG, the
-    other channels EEG-scale white noise) is checked against the oracle."""
+    row of the first recording of each padded length (142 recordings; a
+    channel of structured synthetic EEG, the other channels EEG-scale white
+    noise) is checked against the oracle."""
     recs = synth.batch_recordings()
     assert len(recs) == 256
     rng = np.random.default_rng(9)
-    its, checks = [], []
+    its, checks, seen_L = [], [], set()
     for k, r in enumerate(recs):
         C, N = r["C"], r["N"]
         x = rng.standard_normal((C, N), dtype=np.float32) * np.float32(synth.EEG_RMS_UV)
         plan = cwt.Plan(N, r["sfreq"], r["freqs"], n_cycles=r["n_cycles"], out="power")
         it = dict(plan=plan, xt=torch.from_numpy(x).cuda(), out=plan.alloc_output(C),
                   freqs=r["freqs"], cyc=r["n_cycles"], sfreq=r["sfreq"], mode="power")
-        if k % 8 == 0:
+        if plan.L not in seen_L:
+            seen_L.add(plan.L)
             c, f = int(rng.integers(0, C)), int(rng.integers(0, len(r["freqs"])))
             x_c = synth.eeg(1, N, r["sfreq"], r["seed"])
             it["xt"][c] = torch.from_numpy(x_c[0]).cuda()
@@ -162,7 +164,7 @@ def test_full_recording_draw_one_graph():
         o = it["out"]
         assert bool(torch.isfinite(o).all()) and float(o.min()) >= 0.0
         total += o.numel()
-    assert total > 1.4e10
+    assert total > 1.4e10 and len(checks) == len(seen_L) > 100
     for k, c, f, x_c in checks:
         it = its[k]
         got = it["out"][c, f].cpu().numpy().astype(np.float64)
