@@ -61,6 +61,17 @@ def committed_traffic(plan, out, kind):
     return int(fields["traffic_bytes_per_launch"])
 
 
+def cpu_model():
+    """The host CPU's model name (first entry of /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def kernel_name(plan, fused):
     """The transform kernel the timed steps launch (the one the roofline prices)."""
     if plan.desc.kernel == 1 and fused:
@@ -365,6 +376,46 @@ def bench_stream(n_sessions, C, sfreq, win_s, hop_s, seconds, seed, max_batch, d
         "seconds": seconds, "max_batch": max_batch, "deadline_us": deadline_us}
 
 
+def bench_torch_fft(plan, x, C, N, F, stream, steps, W_ref):
+    """Same-GPU library context: the pipeline composed from torch.fft (the ROCm
+    FFT library) and one broadcast multiply, with the plan's own FP32 spectra
+    scattered into a dense [F, L] table: forward FFT of each channel, product
+    with every frequency's spectrum, batched inverse FFT, crop to N."""
+    import numpy as np
+    import torch
+    L = plan.L
+    H, band, _ = plan.tables()
+    Hd = np.zeros((F, L), dtype=np.float32)
+    for i, (lo, K, off) in enumerate(band):
+        Hd[i, (lo + np.arange(K)) % L] = H[off:off + K]
+    Hg = torch.from_numpy(Hd).to(x.device)
+
+    def run():
+        X = torch.fft.fft(x, n=L)                          # [C, L] complex64
+        Y = X[:, None, :] * Hg[None, :, :]                 # [C, F, L]
+        return torch.fft.ifft(Y, dim=-1, norm="forward")[..., :N]  # 1/L is in H
+
+    with torch.cuda.stream(stream):
+        W = run()
+        torch.cuda.synchronize()
+        e_W = float((W - W_ref).abs().max() / W_ref.abs().max())
+        del W
+        for _ in range(5):
+            run()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            run()
+        e1.record(stream)
+        e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"kind": "torch.fft (ROCm FFT library) composite of the same pipeline, same GPU",
+            "ms_per_step": ms, "value": C * F * N / (ms * 1e-3),
+            "max_rel_diff_vs_this_library": e_W}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -595,6 +646,14 @@ def main():
     del ring, fills
     torch.cuda.empty_cache()
 
+    if args.out == "complex64":
+        W_ref = plan.execute(x)
+        result["library_baseline"] = bench_torch_fft(plan, x, C, N, F, stream, min(K, 50), W_ref)
+        result["library_baseline"]["speedup_of_this_library"] = (
+            result["library_baseline"]["ms_per_step"] / ms_step)
+        del W_ref
+        torch.cuda.empty_cache()
+
     if args.batch_steps > 0:
         result["batch"] = bench_batch(args.batch_steps)
 
@@ -625,7 +684,25 @@ def main():
             "value": passes * len(rows) * N / dt, "unit": "samples*freqs/s",
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "%d pass(es) over %d of %d channels x %d freqs x %d samples (FP64 direct "
-                      "cyclic convolution, %.1f s in all)" % (passes, Cs, C, F, N, dt)}
+                      "cyclic convolution, %.1f s in all)" % (passes, Cs, C, F, N, dt),
+            "cpu_model": cpu_model()}
+        # Context: the paper's own method (FFT, multiply, inverse FFT) in FP64
+        # on the same host cores, with the oracle's closed-form spectra.
+        import scipy.fft as sfft
+        L = plan.L
+        Hb = oracle.wavelet_bank(L, cfg["sfreq"], cfg["freqs"], cfg["n_cycles"])
+        nt = oracle.num_threads()
+        t0 = time.perf_counter()
+        for c in range(C):
+            Xc = sfft.fft(xs[c], n=L)
+            Wc = sfft.ifft(Xc[None, :] * Hb, axis=-1, workers=nt)[:, :N]
+        dt_fft = time.perf_counter() - t0
+        del Wc
+        result["cpu_fft_context"] = {
+            "kind": "scipy.fft FP64 pipeline of the paper's method (forward FFT, multiply, "
+                    "inverse FFT per channel and frequency), whole job, host cores",
+            "value": C * F * N / dt_fft, "unit": "samples*freqs/s", "threads": nt,
+            "seconds": dt_fft}
     plan.close()
     print(json.dumps(result), flush=True)
 
