@@ -16,7 +16,10 @@ per step; the serial step time is reported either way).
 Prints one JSON line with the throughput (output samples x frequencies per
 second), the roofline of the dominant kernel (the transform launch, each timed
 by events bound to its own dispatch on the stream it runs on) and the FP64
-CPU oracle's throughput on a bounded sample of the same workload.
+CPU oracle's throughput on a bounded sample of the same workload; beside them
+the split-precision variants, the 256-recording batch, the length sweep, the
+streaming server's latencies, and as context the same pipeline composed from
+torch.fft on the same GPU and the paper's FFT method in FP64 on the host.
 """
 import argparse
 import json
