@@ -64,6 +64,31 @@ def committed_traffic(plan, out, kind):
     return int(fields["traffic_bytes_per_launch"])
 
 
+def oracle_single_thread(cfg, Cs):
+    """The oracle's rate on one host thread (OMP_NUM_THREADS=1, in a child
+    process, since the thread count is fixed when the oracle loads) over Cs
+    channels x all frequencies of the workload; None if the child fails."""
+    import subprocess
+    code = (
+        "import sys, time, json; sys.path.insert(0, %r)\n"
+        "import numpy as np, synth, oracle\n"
+        "d = synth.eeg_64ch(seed=2, C=%d)\n"
+        "rows = [(c, f) for c in range(%d) for f in range(len(d['freqs']))]\n"
+        "t0 = time.perf_counter()\n"
+        "oracle.cwt(d['x'].astype(np.float64), d['sfreq'], d['freqs'], d['n_cycles'], rows=rows)\n"
+        "dt = time.perf_counter() - t0\n"
+        "print(json.dumps({'value': len(rows) * d['x'].shape[1] / dt, 'seconds': dt,\n"
+        "                  'threads': oracle.num_threads(), 'channels': %d}))\n"
+    ) % (ROOT, Cs, Cs, Cs)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                           text=True, timeout=300)
+        return json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else None
+    except (subprocess.SubprocessError, ValueError, IndexError):
+        return None
+
+
 def cpu_model():
     """The host CPU's model name (first entry of /proc/cpuinfo), or None."""
     try:
@@ -688,7 +713,8 @@ def main():
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "%d pass(es) over %d of %d channels x %d freqs x %d samples (FP64 direct "
                       "cyclic convolution, %.1f s in all)" % (passes, Cs, C, F, N, dt),
-            "cpu_model": cpu_model()}
+            "cpu_model": cpu_model(),
+            "single_thread": oracle_single_thread(cfg, min(2, C))}
         # Context: the paper's own method (FFT, multiply, inverse FFT) in FP64
         # on the same host cores, with the oracle's closed-form spectra.
         import scipy.fft as sfft
