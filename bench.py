@@ -67,7 +67,8 @@ def committed_traffic(plan, out, kind):
 def oracle_single_thread(cfg, Cs):
     """The oracle's rate on one host thread (OMP_NUM_THREADS=1, in a child
     process, since the thread count is fixed when the oracle loads) over Cs
-    channels x all frequencies of the workload; None if the child fails."""
+    channels x all frequencies of the 64-channel workload; None if the child
+    fails.  (cfg is unused: the child regenerates the seeded input.)"""
     import subprocess
     code = (
         "import sys, time, json; sys.path.insert(0, %r)\n"
@@ -452,6 +453,12 @@ def main():
               "GPU, but only the one-GPU share is implemented and measured", file=sys.stderr)
         sys.exit(2)
 
+    # The single-thread oracle timing runs in a child process, started here
+    # before this process touches the GPU.
+    single = None
+    if not args.no_cpu_baseline and not args.copy_calibration:
+        single = oracle_single_thread(None, 2)
+
     import numpy as np
     import torch
 
@@ -714,7 +721,7 @@ def main():
             "sample": "%d pass(es) over %d of %d channels x %d freqs x %d samples (FP64 direct "
                       "cyclic convolution, %.1f s in all)" % (passes, Cs, C, F, N, dt),
             "cpu_model": cpu_model(),
-            "single_thread": oracle_single_thread(cfg, min(2, C))}
+            "single_thread": single}
         # Context: the paper's own method (FFT, multiply, inverse FFT) in FP64
         # on the same host cores, with the oracle's closed-form spectra.
         import scipy.fft as sfft
