@@ -275,3 +275,40 @@ def test_sampled_wavelet_plan_validation_without_gpu():
     assert f(ctypes.byref(h), 100, 1000.0, fp, 2, wp, 8, ctypes.byref(o), None) == \
         _lib.CWT_E_UNSUPPORTED
     assert not h.value
+
+
+def test_no_fallback_without_the_library():
+    """Without libcwt.so the binding raises instead of computing anything
+    another way: planning and execution both need the HIP library."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2506_07793_amd import _lib\n"
+        "_lib.LIB_PATH = '/nonexistent/libcwt.so'; _lib._lib = None\n"
+        "import paper_2506_07793_amd as cwt\n"
+        "try:\n"
+        "    cwt.Plan(1000, 1000.0, [10.0], n_cycles=7.0)\n"
+        "except ImportError as e:\n"
+        "    print('raised:', e)\n"
+        "else:\n"
+        "    print('no error')\n") % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "raised:" in r.stdout and "not built" in r.stdout, r.stdout
+
+
+def test_product_package_does_not_use_the_oracle():
+    """The oracle is test infrastructure: nothing in the product package (the
+    binding or the HIP/C++ sources) imports, links or names it."""
+    pkg = os.path.join(ROOT, "paper_2506_07793_amd")
+    hits = []
+    for dirpath, _, files in os.walk(pkg):
+        if "_build" in dirpath or "__pycache__" in dirpath:
+            continue
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".cpp", ".hpp", ".h", ".c")):
+                text = open(os.path.join(dirpath, fn), encoding="utf-8").read()
+                if "oracle" in text or "orc_" in text:
+                    hits.append(fn)
+    assert not hits, hits
