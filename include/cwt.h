@@ -328,15 +328,27 @@ typedef struct cwt_batch_item {
 size_t cwt_batch_workspace_size(const cwt_batch_item *items, int32_t n);
 
 /*
- * Transform every item with one HIP graph launch of persistent kernels:
- * tasks (channel pairs for the forward transforms, (channel, output row) for
- * the transforms) are grouped by workgroup size and claimed by resident
- * workgroups through atomic counters, longest first.  The graph is captured
- * the first time a (workspace, task layout) pair is seen and replayed
- * afterwards; the per-item tables are uploaded into ws on `stream` before
- * each launch.  Asynchronous; the items' buffers must not overlap each other
- * or ws.  The environment variable CWT_BATCH_GRAPH=0 launches the kernels
- * directly instead of through the graph.
+ * Transform every item (recordings of uneven length, channel count and
+ * frequency grid, the flexibility discussed in the paper's section
+ * "Wavelength and flexibility") with one HIP graph launch.  Default form:
+ * one forward and one transform launch per item inside the graph, each at
+ * the item's own workgroup size and LDS, its parameters read from the table
+ * uploaded into ws; items longest first, each on the least loaded of four
+ * parallel graph branches.  With the environment variable
+ * CWT_BATCH_KERNELS=persistent: one persistent forward and one transform
+ * kernel per workgroup-size class instead, whose resident workgroups claim
+ * tasks (channel pairs; runs of output rows) through atomic counters,
+ * longest first.  The graph is captured the first time a (workspace, task
+ * layout) pair is seen and replayed afterwards; the per-item tables are
+ * uploaded into ws on `stream` before each launch.  Asynchronous; the items'
+ * buffers must not overlap each other or ws.  Results equal cwt_execute's
+ * for each item.  CWT_BATCH_GRAPH=0 launches the kernels directly instead of
+ * through the graph.  Errors (nothing is launched): CWT_E_INVALID for a
+ * null item, plan or device pointer, C outside [0, 2^24], a null or
+ * misaligned ws or one smaller than cwt_batch_workspace_size;
+ * CWT_E_UNSUPPORTED for a plan that is not FP32 or more than 2^31 - 1
+ * (channel, row) tasks in one item.  CWT_E_HIP for a failed launch or
+ * capture.
  */
 int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *ws, size_t ws_bytes,
                       void *stream);
