@@ -122,7 +122,17 @@ typedef struct cwt_plan cwt_plan;
  * whose magnitude is at least 1e-12 of the peak) and the twiddle table
  * exp(2 pi i m / L) (FP64 on the GPU, rounded once).  Their generation is
  * enqueued on `stream`; the plan may be used on any stream once `stream` has
- * reached that point (cwt_plan_create does not synchronise).
+ * reached that point (cwt_plan_create does not synchronise).  The spectra
+ * are the Fourier-domain wavelets of section "Fourier transformed formula"
+ * (Morlet, Gabor, GMW equations), sampled on the DFT bins.
+ *
+ * Environment, read when a plan is created: CWT_GENERIC_ONLY=1 makes
+ * power-of-two lengths use the runtime-radix kernel instead of the
+ * register-resident one; CWT_FIXED_VARIANT=0 makes the register-resident
+ * kernel read every later-pass twiddle from the table (default 1: one table
+ * value per butterfly, its powers by products); CWT_AUTOTUNE_CACHE names the
+ * autotuner's cache file (see cwt_plan_autotune).  Each changes the rounding
+ * of the results, not their tolerance.
  */
 int cwt_plan_create(cwt_plan **out, int64_t n, double sfreq, const double *freqs,
                     int32_t n_freqs, const double *n_cycles, double omega0,
