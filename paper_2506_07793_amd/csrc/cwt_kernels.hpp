@@ -113,6 +113,8 @@ struct StreamBPParams {
     const int *grp_freq;
     const int *grp_off;
     int n_bands;
+    int n_grouped;         // frequencies in some band (grp_off[n_bands])
+    float *part;           // [rows][n_grouped] workspace: sum over the hop of |W_f[t]|^2
     float *out;            // [rows][n_bands]
 };
 

@@ -41,12 +41,13 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 // Batch workspace of one (plan, C, hop) class.
 struct StreamClass {
     const cwt_plan *plan = nullptr;
-    int C = 0, hop = 0, W = 0, Lh = 0, nb = 0, max_batch = 0;
+    int C = 0, hop = 0, W = 0, Lh = 0, nb = 0, ng = 0, max_batch = 0;  // ng: frequencies in bands
     float *d_slab = nullptr;
     StreamJob *d_jobs = nullptr;
     float *d_xb = nullptr;
     float2 *d_Xh = nullptr;
     float *d_out = nullptr;
+    float *d_part = nullptr;  // [rows][ng] per-frequency sums over the hop
     float *h_slab = nullptr;
     StreamJob *h_jobs = nullptr;
     float *h_out = nullptr;
@@ -54,11 +55,12 @@ struct StreamClass {
     int n_sessions = 0;
 };
 
-size_t class_dev_bytes(int max_batch, int C, int hop, int W, int Lh, int nb)
+size_t class_dev_bytes(int max_batch, int C, int hop, int W, int Lh, int nb, int ng)
 {
     const size_t mb = (size_t)max_batch, c = (size_t)C;
     return align256(mb * c * hop * 4) + align256(mb * sizeof(StreamJob)) +
-           align256(mb * c * W * 4) + align256(mb * c * Lh * 8) + align256(mb * c * nb * 4);
+           align256(mb * c * W * 4) + align256(mb * c * Lh * 8) + align256(mb * c * nb * 4) +
+           align256(mb * c * ng * 4);
 }
 
 struct PendingHop {
@@ -116,7 +118,7 @@ namespace {
 
 void free_class(StreamClass &k)
 {
-    void *dptr[] = {k.d_slab, k.d_jobs, k.d_xb, k.d_Xh, k.d_out};
+    void *dptr[] = {k.d_slab, k.d_jobs, k.d_xb, k.d_Xh, k.d_out, k.d_part};
     for (void *p : dptr)
         if (p) (void)hipFree(p);
     void *hptr[] = {k.h_slab, k.h_jobs, k.h_out};
@@ -135,7 +137,8 @@ int alloc_class(StreamClass &k)
                {(void **)&k.d_jobs, mb * sizeof(StreamJob)},
                {(void **)&k.d_xb, mb * c * k.W * 4},
                {(void **)&k.d_Xh, mb * c * k.Lh * 8},
-               {(void **)&k.d_out, mb * c * k.nb * 4}};
+               {(void **)&k.d_out, mb * c * k.nb * 4},
+               {(void **)&k.d_part, mb * c * k.ng * 4}};
     for (auto &d : dev) {
         if (hipMalloc(d.p, std::max<size_t>(d.n, 256)) != hipSuccess) {
             *d.p = nullptr;
@@ -212,6 +215,8 @@ int run_batch(cwt_server *srv, StreamClass &k, std::vector<PendingHop> &batch,
         bp.grp_freq = P.d_grp_freq;
         bp.grp_off = P.d_grp_off;
         bp.n_bands = nb;
+        bp.n_grouped = k.ng;
+        bp.part = k.d_part;
         bp.out = k.d_out;
         if ((e = launch_stream_bandpower(bp, P.max_bins, s)) != hipSuccess)
             return hip_fail(e, "band power launch");
@@ -410,7 +415,9 @@ extern "C" int cwt_stream_open(cwt_server *srv, const cwt_plan *plan, int64_t C,
         if (k->plan == plan && k->C == C && k->hop == hop) cls = k.get();
     const int Lh = plan->L / 2 + 1;
     const size_t ring_bytes = align256((size_t)C * W * 4);
-    const size_t cls_bytes = cls ? 0 : class_dev_bytes(mb, (int)C, (int)hop, (int)W, Lh, plan->n_bands);
+    const int ng = plan->grp_off.empty() ? 0 : plan->grp_off.back();
+    const size_t cls_bytes =
+        cls ? 0 : class_dev_bytes(mb, (int)C, (int)hop, (int)W, Lh, plan->n_bands, ng);
     if (srv->used + ring_bytes + cls_bytes > srv->budget)
         return fail(CWT_E_BUDGET, "session needs %zu bytes, %zu of %zu in use",
                     ring_bytes + cls_bytes, srv->used, srv->budget);
@@ -429,6 +436,7 @@ extern "C" int cwt_stream_open(cwt_server *srv, const cwt_plan *plan, int64_t C,
         fresh->W = (int)W;
         fresh->Lh = Lh;
         fresh->nb = plan->n_bands;
+        fresh->ng = ng;
         fresh->max_batch = mb;
         fresh->dev_bytes = cls_bytes;
         int rc = alloc_class(*fresh);
