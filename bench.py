@@ -660,6 +660,7 @@ def main():
     # DFT-as-GEMM (MFMA) transform kernel.  Their errors against the FP64
     # oracle are measured by tests/test_gpu_split.py.
     prec_runs = []
+    W32 = plan.execute(x) if args.out == "complex64" else None
     for prec in ("split_f16", "split_bf16"):
         pp = cwt.Plan(N, cfg["sfreq"], cfg["freqs"], n_cycles=cfg["n_cycles"], out=args.out,
                       precision=prec)
@@ -673,12 +674,24 @@ def main():
                 j = i % RING
                 pp.transform_spectra(C, ring[j * ob:(j + 1) * ob], ws, stream=stream)
             ms_p = float(np.mean(pp.timing_stop()))
-        prec_runs.append({"precision": prec, "transform_ms": ms_p,
-                          "transform_pts_per_s": pts / (ms_p * 1e-3),
-                          "hbm_frac": transform_bytes / (ms_p * 1e-3) / 1e9 / HBM_PEAK_GBS})
+        run = {"precision": prec, "transform_ms": ms_p,
+               "transform_pts_per_s": pts / (ms_p * 1e-3),
+               "hbm_frac": transform_bytes / (ms_p * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        if W32 is not None:
+            # difference from the FP32 path's output on the same input (its
+            # error against the FP64 oracle is what tests/test_gpu_split.py gates)
+            Wp = pp.execute(x)
+            torch.cuda.synchronize()
+            P32, Pp = W32.abs() ** 2, Wp.abs() ** 2
+            run["vs_fp32_path"] = {
+                "max_rel_W": float((Wp - W32).abs().max() / W32.abs().max()),
+                "max_rel_P": float((Pp - P32).abs().max() / P32.max()),
+                "mean_rel_P": float((Pp - P32).abs().mean() / P32.max())}
+            del Wp, P32, Pp
+        prec_runs.append(run)
         pp.close()
     result["precision_variants"] = prec_runs
-    del ring, fills
+    del ring, fills, W32
     torch.cuda.empty_cache()
 
     if args.out == "complex64":
