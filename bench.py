@@ -130,6 +130,9 @@ def parse():
                     help="1: replay the step as a captured HIP graph; 0: direct launches (default)")
     ap.add_argument("--batch-steps", type=int, default=3,
                     help="timed steps of the 256-recording batch run (0 skips it)")
+    ap.add_argument("--stream-deadline-us", type=int, default=500,
+                    help="streaming server's batching deadline in microseconds (the longest "
+                         "a completed hop waits for others to share its launch)")
     ap.add_argument("--stream-seconds", type=float, default=6.0,
                     help="real-time length of each streaming run (0 skips the streaming runs)")
     ap.add_argument("--length-sweep", type=int, default=1,
@@ -710,8 +713,10 @@ def main():
 
     if args.stream_seconds > 0:
         result["stream"] = [
-            bench_stream(512, 64, 1000.0, 2.0, 0.05, args.stream_seconds, 5, 512, 1000),
-            bench_stream(64, 256, 2048.0, 2.0, 102 / 2048.0, args.stream_seconds, 6, 64, 1000),
+            bench_stream(512, 64, 1000.0, 2.0, 0.05, args.stream_seconds, 5, 512,
+                         args.stream_deadline_us),
+            bench_stream(64, 256, 2048.0, 2.0, 102 / 2048.0, args.stream_seconds, 6, 64,
+                         args.stream_deadline_us),
         ]
         result["p99_stream_ms"] = result["stream"][0]["p99_ms"]
 
