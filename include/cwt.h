@@ -379,7 +379,7 @@ typedef struct cwt_session cwt_session;
 
 typedef struct cwt_server_opts {
     int32_t max_batch;        /* sessions per launch (default 256)                   */
-    int32_t deadline_us;      /* longest wait of a pending hop before launch (1000)  */
+    int32_t deadline_us;      /* longest wait of a pending hop before launch (500)   */
     int32_t max_pending;      /* queued hops per session before CWT_E_AGAIN (64)     */
     int32_t reserved_;
 } cwt_server_opts;

@@ -305,7 +305,7 @@ extern "C" int cwt_server_opts_init(cwt_server_opts *o)
     if (!o) return fail(CWT_E_INVALID, "cwt_server_opts_init: NULL");
     std::memset(o, 0, sizeof *o);
     o->max_batch = 256;
-    o->deadline_us = 1000;
+    o->deadline_us = 500;
     o->max_pending = 64;
     return CWT_OK;
 }

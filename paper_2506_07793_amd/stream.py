@@ -14,7 +14,7 @@ def now_ns():
 class Server:
     """Batching stream server with an HBM budget (device memory of rings + workspaces)."""
 
-    def __init__(self, hbm_budget_bytes, max_batch=256, deadline_us=1000, max_pending=64):
+    def __init__(self, hbm_budget_bytes, max_batch=256, deadline_us=500, max_pending=64):
         lib = _lib.load()
         self._lib = lib
         o = _lib.ServerOpts()

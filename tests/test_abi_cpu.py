@@ -214,7 +214,7 @@ def test_stream_validation_without_gpu():
     assert lib.cwt_server_create(None, 1 << 20, None) == INV
     o = _lib.ServerOpts()
     lib.cwt_server_opts_init(ctypes.byref(o))
-    assert (o.max_batch, o.deadline_us, o.max_pending) == (256, 1000, 64)
+    assert (o.max_batch, o.deadline_us, o.max_pending) == (256, 500, 64)
     o.max_batch = 0
     assert lib.cwt_server_create(ctypes.byref(h), 1 << 20, ctypes.byref(o)) == INV
     lib.cwt_server_opts_init(ctypes.byref(o))
