@@ -24,9 +24,15 @@ Paper sections followed:
     stated reading, see ``DEFAULT_BANDS``).
 
 Parity pins: every function here is checked in ``tests/test_oracle_pins.py``
-against closed forms, quadrature, brute force and invariants.  The band and
-stream reductions are plain means of the pinned power and are "parity
-unpinned" beyond that (the paper prints no band-power values).
+against closed forms, quadrature, brute force and invariants.  The band
+membership, band mean and streaming trailing-hop mean are pinned against the
+closed form of exact-bin tones (whose beats make the power change within a
+hop) with a hand-written band membership that puts a grid frequency on every
+band edge; ``tests/test_oracle_mutants.py`` plants mistakes in them too.
+
+``parity_errors`` compares in absolute terms when the reference is all zero
+(for instance a Morlet transform of a one-sample signal: the wavelet spectrum
+vanishes at zero frequency, so the whole transform is zero).
 """
 import ctypes
 import os

@@ -49,6 +49,9 @@ PIN_CALLS = [
     (pins.test_gmw_moments_match_gamma_functions, dict(beta=8.0, gamma=2.0)),
     (pins.test_gmw_vanishes_at_nonpositive_frequencies, {}),
     (pins.test_gmw_tone_closed_form, dict(beta=17.5, gamma=3.0)),
+    (pins.test_band_groups_on_the_edges, {}),
+    (pins.test_band_power_tone_closed_form, {}),
+    (pins.test_stream_band_power_tone_closed_form, {}),
 ]
 
 MUTANTS = {
@@ -112,3 +115,45 @@ def test_planted_mistake_fails_a_pin(name, tmp_path):
 def test_real_oracle_passes_the_same_pins():
     for fn, kw in PIN_CALLS:
         fn(oracle, **kw)
+
+
+# Planted mistakes in the oracle's Python reductions (band membership, band
+# mean, power, the streaming trailing-hop window and its mean).  The mutated
+# module source is loaded as a sibling module sharing the real C library.
+PY_MUTANTS = {
+    "band_sum_not_mean": ("P[:, g, :].mean(axis=1)", "P[:, g, :].sum(axis=1)"),
+    "last_band_open_at_hi": ("(freqs >= lo) & (freqs <= hi)", "(freqs >= lo) & (freqs < hi)"),
+    "band_lo_exclusive": ("m = (freqs >= lo) & (freqs < hi)", "m = (freqs > lo) & (freqs < hi)"),
+    "band_hi_inclusive": ("m = (freqs >= lo) & (freqs < hi)", "m = (freqs >= lo) & (freqs <= hi)"),
+    "power_drops_imag": ("W.real ** 2 + W.imag ** 2", "W.real ** 2"),
+    "stream_window_one_early": ("t0=Wn - hop, nt=hop", "t0=Wn - hop - 1, nt=hop"),
+    "stream_window_one_late": ("t0=Wn - hop, nt=hop", "t0=Wn - hop + 1, nt=hop - 1"),
+    "stream_leading_hop": ("t0=Wn - hop, nt=hop", "t0=0, nt=hop"),
+    "stream_hop_sum": ("return bp.mean(axis=2)", "return bp.sum(axis=2)"),
+}
+
+
+def _load_py_mutant(name):
+    import importlib.util as iu
+    import types
+    old, new = PY_MUTANTS[name]
+    src = open(oracle.__file__).read()
+    assert src.count(old) == 1, name
+    mod = types.ModuleType("oracle._mutant_" + name)
+    mod.__package__ = "oracle"
+    mod.__file__ = oracle.__file__
+    exec(compile(src.replace(old, new), oracle.__file__, "exec"), mod.__dict__)
+    mod._lib = oracle._load()
+    return mod
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTANTS))
+def test_planted_reduction_mistake_fails_a_pin(name):
+    mut = _load_py_mutant(name)
+    failed = []
+    for fn, kw in PIN_CALLS:
+        try:
+            fn(mut, **kw)
+        except AssertionError:
+            failed.append(fn.__name__)
+    assert failed, "mutant %s passed every pin" % name

@@ -314,16 +314,111 @@ def test_band_groups_counts(orc):
     assert sorted(np.concatenate(g).tolist()) == list(range(40))
 
 
-def test_band_power_is_mean_of_power(orc):
-    """Parity unpinned beyond the definition: band power is the plain mean of power."""
-    x = _rand(7, 2, 256)
-    freqs = synth.log_freqs(1.0, 100.0, 12)
-    P = orc.power(orc.cwt(x, 256.0, freqs, synth.eeg_cycles(freqs)))
-    g = orc.band_groups(freqs)
-    BP = orc.band_power(P, g)
-    for b, idx in enumerate(g):
-        if len(idx):
-            assert np.allclose(BP[:, b], P[:, idx].sum(axis=1) / len(idx), rtol=1e-14)
+# Band power and the streaming trailing-hop value, pinned against the tone
+# closed form.  For L = N and tones x = sum_k A_k sin(w_k t + phi_k) on exact
+# DFT bins b_k, the cyclic convolution with h = IDFT(H_f) is
+#   W_f[t] = sum_k (A_k / 2i) (e^{i phi_k} H_f[b_k] e^{i w_k t}
+#                              - e^{-i phi_k} H_f[L - b_k] e^{-i w_k t}),
+# evaluated here with no convolution.  Band membership of the grid is written
+# out by hand (not computed by a rule) for the edge reading delta [1, 4),
+# theta [4, 8), alpha [8, 13), beta [13, 30), gamma [30, 100], and the grid has
+# a frequency on every edge.  Tones close in frequency beat, so |W|^2 changes
+# within a 50-sample hop: a window shifted by one sample, a sum for a mean or a
+# band closed at the wrong end each change the result far beyond the 1e-12
+# bar.
+
+BAND_GRID = np.array([1.0, 2.5, 3.999, 4.0, 6.0, 7.5, 8.0, 10.0, 12.5, 13.0, 21.0, 29.5,
+                      30.0, 60.0, 100.0])
+BAND_MEMBERS = [[0, 1, 2], [3, 4, 5], [6, 7, 8], [9, 10, 11], [12, 13, 14]]
+# (frequency Hz, amplitude, phase) per channel; every frequency is a bin of
+# L = 2000 at 1000 Hz (0.5 Hz spacing)
+BAND_TONES = [
+    [(2.5, 1.2, 0.3), (6.0, 0.7, 1.1), (9.5, 1.0, 0.0), (11.0, 0.8, 2.0), (17.5, 0.5, 0.4),
+     (23.0, 0.45, 2.9), (41.0, 0.3, 1.7), (57.5, 0.25, 0.2)],
+    [(3.5, 0.9, 2.2), (7.0, 0.6, 0.5), (10.5, 1.1, 1.3), (12.0, 0.4, 0.8), (26.0, 0.5, 1.9),
+     (35.0, 0.35, 0.6), (58.5, 0.2, 2.4), (99.5, 0.15, 1.0)],
+]
+
+
+def _tone_signal(N, sfreq, tones):
+    t = np.arange(N) / sfreq
+    return np.stack([sum(A * np.sin(2 * np.pi * f0 * t + ph) for f0, A, ph in ch)
+                     for ch in tones])
+
+
+def _tone_closed_form(orc, N, sfreq, freqs, cycles, tones):
+    """[C, F, N] complex W from the tone closed form (L = N, exact bins)."""
+    t = np.arange(N)
+    W = np.zeros((len(tones), len(freqs), N), dtype=np.complex128)
+    for fi, (f, s) in enumerate(zip(freqs, cycles)):
+        H = orc.wavelet_spectrum(N, sfreq, f, s)
+        for c, ch in enumerate(tones):
+            for f0, A, ph in ch:
+                b0 = int(round(f0 * N / sfreq))
+                assert abs(b0 * sfreq / N - f0) < 1e-12  # exact bin
+                w0 = 2 * np.pi * b0 * t / N
+                W[c, fi] += A / 2j * (np.exp(1j * ph) * H[b0] * np.exp(1j * w0)
+                                      - np.exp(-1j * ph) * H[N - b0] * np.exp(-1j * w0))
+    return W
+
+
+def _hand_band_means(P):
+    """[C, F, ...] power -> [C, 5, ...] by the hand-written membership."""
+    return np.stack([sum(P[:, i] for i in m) / len(m) for m in BAND_MEMBERS], axis=1)
+
+
+def test_band_groups_on_the_edges(orc):
+    """Each grid frequency lands in the band written out by hand, edges included."""
+    got = [list(g) for g in orc.band_groups(BAND_GRID)]
+    assert got == BAND_MEMBERS
+
+
+def test_band_power_tone_closed_form(orc):
+    """Band power = mean over the band's grid frequencies of |W|^2, against the
+    tone closed form (every output sample, both channels)."""
+    N, sfreq = 2000, 1000.0
+    cyc = synth.eeg_cycles(BAND_GRID)
+    x = _tone_signal(N, sfreq, BAND_TONES)
+    Wref = _tone_closed_form(orc, N, sfreq, BAND_GRID, cyc, BAND_TONES)
+    ref = _hand_band_means(np.abs(Wref) ** 2)
+    got = orc.band_power(orc.power(orc.cwt(x, sfreq, BAND_GRID, cyc)),
+                         orc.band_groups(BAND_GRID))
+    assert got.shape == ref.shape == (2, 5, N)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(ref)
+    for b in range(5):  # every band, not just the strongest
+        assert np.max(np.abs(got[:, b] - ref[:, b])) <= 1e-10 * np.max(ref[:, b])
+
+
+def test_band_power_varies_within_a_hop(orc):
+    """The pin below is sensitive to the window position: the closed-form band
+    power changes by far more than 1e-12 when the 50-sample window moves by
+    one sample."""
+    N, sfreq, hop = 2000, 1000.0, 50
+    cyc = synth.eeg_cycles(BAND_GRID)
+    BP = _hand_band_means(np.abs(_tone_closed_form(orc, N, sfreq, BAND_GRID, cyc,
+                                                   BAND_TONES)) ** 2)
+    cur = BP[:, :, N - hop:].mean(axis=2)
+    early = BP[:, :, N - hop - 1:N - 1].mean(axis=2)
+    assert np.min(np.abs(cur - early) / cur) > 1e-7
+
+
+def test_stream_band_power_tone_closed_form(orc):
+    """Streaming value: band power averaged over the window's last `hop`
+    samples (t in [W - hop, W)), against the tone closed form."""
+    N, sfreq, hop = 2000, 1000.0, 50
+    cyc = synth.eeg_cycles(BAND_GRID)
+    x = _tone_signal(N, sfreq, BAND_TONES)
+    Wref = _tone_closed_form(orc, N, sfreq, BAND_GRID, cyc, BAND_TONES)
+    ref = np.zeros((2, 5))
+    for c in range(2):
+        for b, m in enumerate(BAND_MEMBERS):
+            acc = 0.0
+            for t in range(N - hop, N):
+                acc += sum(abs(Wref[c, i, t]) ** 2 for i in m) / len(m)
+            ref[c, b] = acc / hop
+    got = orc.stream_band_power(x, sfreq, BAND_GRID, cyc, hop)
+    assert got.shape == (2, 5)
+    assert np.max(np.abs(got - ref) / ref) <= 1e-11
 
 
 # --------------------------------------------------------------- fixtures --
