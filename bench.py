@@ -11,7 +11,11 @@ buffer of a 64-buffer ring (13.4 GB, beyond the 256 MB last-level cache), so
 that the outputs reach HBM.  By default the K timed steps run as
 cwt_execute_batches: one launch per step that transforms the step's batch and
 computes the next batch's forward FFT (--serial: forward + transform launches
-per step; the serial step time is reported either way).
+per step; the serial step time is reported either way).  Before the warm-up
+steps a pre-roll of untimed pipelined steps runs until at least --preroll-ms
+of GPU time has passed and two consecutive chunk means agree within 2% (on a
+fresh device the first ~25 ms of work run 15-30% slower while the clock
+ramps up); it is reported as `preroll`, and `warmup` stays what was asked.
 
 Prints one JSON line with the throughput (output samples x frequencies per
 second), the roofline of the dominant kernel (the transform launch, each timed
@@ -137,6 +141,10 @@ def parse():
                     help="real-time length of each streaming run (0 skips the streaming runs)")
     ap.add_argument("--length-sweep", type=int, default=1,
                     help="1: run the N = 100..2500 length sweep (0 skips it)")
+    ap.add_argument("--preroll-ms", type=float, default=300.0,
+                    help="untimed pipelined steps before the warm-up until at least this much "
+                         "GPU time has passed and two consecutive chunk means agree within 2%% "
+                         "(the device clock ramps up over the first tens of ms of work)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (scales the HBM "
                          "byte counters of a profiler run)")
@@ -535,9 +543,26 @@ def main():
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1)
 
+    def preroll(min_ms, tol=0.02, max_ms=3000.0):
+        """Untimed pipelined steps, one ring pass per chunk, until at least
+        min_ms of GPU time has passed and the last two chunk means agree
+        within tol (at most max_ms)."""
+        total, n, means = 0.0, 0, []
+        while True:
+            ms = timed(lambda: batches(RING))
+            total += ms
+            n += RING
+            means.append(ms / RING)
+            settled = len(means) >= 2 and abs(means[-1] - means[-2]) <= tol * means[-2]
+            if (total >= min_ms and settled) or total >= max_ms:
+                break
+        return {"gpu_ms": total, "steps": n, "settled": settled,
+                "last_two_chunk_ms_per_step": means[-2:]}
+
     K = args.steps
     serial = not args.graph and args.serial
     with torch.cuda.stream(stream):
+        pre = preroll(args.preroll_ms) if args.preroll_ms > 0 else None
         for _ in range(args.warmup):
             step()
         batches(args.warmup)
@@ -648,7 +673,15 @@ def main():
                      "traffic": committed_traffic(plan, args.out, "fused" if fused else "main"),
                      "algorithmic_bytes": main_bytes, "avg_ms": ms_main,
                      "median_ms": float(np.median(kernel_ms)),
-                     "p90_ms": float(np.percentile(kernel_ms, 90))},
+                     "p90_ms": float(np.percentile(kernel_ms, 90)),
+                     # the kernel's launches cannot take longer than the steps that
+                     # contain them; False flags a run whose clock changed between
+                     # the timed pass and the event pass
+                     "kernel_avg_within_step": bool(ms_main <= ms_step),
+                     # the same algorithmic bytes over the whole step (launch gaps
+                     # included), the figure the step clock gives
+                     "step_frac": main_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "preroll": pre,
         "step_hbm_frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "output_ring": {"buffers": RING, "MB": RING * ob / 1e6},
         "one_output_buffer": one_buf,

@@ -32,6 +32,37 @@ def _dptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _nbytes(t):
+    return t.numel() * t.element_size()
+
+
+def _check_dev(name, t, device=None, dtype=None, min_bytes=None, contiguous=True):
+    """A tensor handed to the library as a device pointer: on a GPU, on
+    `device` (when given), of `dtype` (when given), contiguous, and at least
+    `min_bytes` long.  Raises before anything is launched."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if not t.is_cuda:
+        raise TypeError("%s must be a cuda tensor (got device %s)" % (name, t.device))
+    if device is not None and t.device != device:
+        raise ValueError("%s is on %s, expected %s" % (name, t.device, device))
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s (got %s)" % (name, dtype, t.dtype))
+    if contiguous and not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if min_bytes is not None and _nbytes(t) < min_bytes:
+        raise ValueError("%s holds %d bytes, the call writes or reads %d" % (
+            name, _nbytes(t), min_bytes))
+    return t
+
+
+def _on_other_stream(stream):
+    """True when `stream` is given and is not torch's current stream."""
+    import torch
+    return stream is not None and stream != torch.cuda.current_stream()
+
+
 def _make_opts(lib, wavelet, pad, explicit_len, out, precision, bands, gmw_beta=17.5,
                gmw_gamma=3.0):
     opts = _lib.PlanOpts()
@@ -189,14 +220,20 @@ class Plan:
         """n_batches batches of C channels (cwt_execute_batches): batch i
         reads x at i * x_batch_stride floats and writes out at
         i * out_batch_stride bytes (defaults: consecutive batches)."""
+        import torch
         if x_batch_stride is None:
             x_batch_stride = int(C) * self.n
         if out_batch_stride is None:
             out_batch_stride = self.output_bytes(C)
+        nb = max(int(n_batches), 1)
+        _check_dev("x", x, dtype=torch.float32,
+                   min_bytes=4 * (int(C) * self.n + (nb - 1) * int(x_batch_stride)))
+        _check_dev("ws", ws, device=x.device, min_bytes=self.batches_workspace_size(C))
+        _check_dev("out", out, device=x.device,
+                   min_bytes=self.output_bytes(C) + (nb - 1) * int(out_batch_stride))
         _lib.check(self._lib.cwt_execute_batches(
             self._ptr, _dptr(x), int(x_batch_stride), int(n_batches), int(C), _dptr(out),
-            int(out_batch_stride), _dptr(ws), ws.numel() * ws.element_size(),
-            _stream_handle(stream)))
+            int(out_batch_stride), _dptr(ws), _nbytes(ws), _stream_handle(stream)))
         return out
 
     def timing_start(self, max_launches):
@@ -236,9 +273,32 @@ class Plan:
         elem = 8 if self.out_mode == "complex64" else 4
         return int(C) * self.out_rows * self.n * elem
 
-    def output_bytes(self, C):
-        elem = 8 if self.out_mode == "complex64" else 4
-        return int(C) * self.out_rows * self.n * elem
+    @property
+    def out_dtype(self):
+        import torch
+        return torch.complex64 if self.out_mode == "complex64" else torch.float32
+
+    def _check_x(self, x):
+        """x: cuda float32 [C, n] contiguous; returns C."""
+        import torch
+        _check_dev("x", x, dtype=torch.float32)
+        if x.dim() != 2 or x.shape[1] != self.n:
+            raise ValueError("x must have shape [C, %d] (got %s)" % (self.n, tuple(x.shape)))
+        return int(x.shape[0])
+
+    def _check_out(self, out, C, device, n_batches=1, stride=None):
+        need = self.output_bytes(C) + (n_batches - 1) * (stride or 0)
+        _check_dev("out", out, device=device, min_bytes=need)
+        if n_batches == 1 and stride is None:
+            if out.dtype != self.out_dtype:
+                raise TypeError("out must be %s for output mode %r (got %s)" % (
+                    self.out_dtype, self.out_mode, out.dtype))
+            if tuple(out.shape) != self.output_shape(C):
+                raise ValueError("out must have shape %s (got %s)" % (
+                    self.output_shape(C), tuple(out.shape)))
+
+    def _check_ws(self, ws, device, need):
+        _check_dev("ws", ws, device=device, min_bytes=need)
 
     def alloc_output(self, C, device="cuda"):
         import torch
@@ -251,38 +311,53 @@ class Plan:
         return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
     def execute(self, x, out=None, ws=None, stream=None):
-        """x: cuda float32 [C, n] (or [n]).  Returns the output tensor."""
+        """x: cuda float32 [C, n] (or [n]).  Returns the output tensor.
+
+        out and ws (when given) must be cuda tensors on x's device: out of the
+        plan's output dtype and shape, ws of at least workspace_size(C)
+        bytes.  Tensors this call allocates are marked as used by `stream`
+        so that torch's allocator does not reuse them before the launch has
+        finished there."""
         import torch
-        if x.dim() == 1:
+        if isinstance(x, torch.Tensor) and x.dim() == 1:
             x = x[None, :]
-        if x.dtype != torch.float32 or not x.is_cuda:
-            raise TypeError("x must be a cuda float32 tensor")
-        if x.shape[-1] != self.n:
-            raise ValueError("x has %d samples, plan expects %d" % (x.shape[-1], self.n))
-        x = x.contiguous()
+        _check_dev("x", x, dtype=torch.float32, contiguous=False)
+        if x.dim() != 2 or x.shape[1] != self.n:
+            raise ValueError("x has shape %s, plan expects [C, %d]" % (tuple(x.shape), self.n))
+        other = _on_other_stream(stream)
+        made = []
+        if not x.is_contiguous():
+            x = x.contiguous()
+            made.append(x)
         C = int(x.shape[0])
         if out is None:
             out = self.alloc_output(C, device=x.device)
-        if tuple(out.shape) != self.output_shape(C) or not out.is_contiguous():
-            raise ValueError("out must be contiguous with shape %s" % (self.output_shape(C),))
+        self._check_out(out, C, x.device)
         if ws is None:
             ws = self.alloc_workspace(C, device=x.device)
+            made.append(ws)
+        self._check_ws(ws, x.device, self.workspace_size(C))
         _lib.check(self._lib.cwt_execute(self._ptr, _dptr(x), C, _dptr(out), _dptr(ws),
-                                         ws.numel() * ws.element_size(), _stream_handle(stream)))
+                                         _nbytes(ws), _stream_handle(stream)))
+        if other:
+            for t in made:
+                t.record_stream(stream)
         return out
 
     def forward_spectra(self, x, ws, stream=None):
         """Stage 1 of execute: channel half spectra into ws (cwt_forward_spectra)."""
-        C = int(x.shape[0])
+        C = self._check_x(x)
+        self._check_ws(ws, x.device, self.workspace_size(C))
         _lib.check(self._lib.cwt_forward_spectra(self._ptr, _dptr(x), C, _dptr(ws),
-                                                 ws.numel() * ws.element_size(),
-                                                 _stream_handle(stream)))
+                                                 _nbytes(ws), _stream_handle(stream)))
 
     def transform_spectra(self, C, out, ws, stream=None):
-        """Stage 2 of execute: spectra in ws -> out (cwt_transform_spectra)."""
+        """Stage 2 of execute: spectra in ws -> out (cwt_transform_spectra).
+        out may be any cuda buffer of at least output_bytes(C) bytes."""
+        _check_dev("ws", ws, min_bytes=self.workspace_size(C))
+        _check_dev("out", out, device=ws.device, min_bytes=self.output_bytes(C))
         _lib.check(self._lib.cwt_transform_spectra(self._ptr, int(C), _dptr(out), _dptr(ws),
-                                                   ws.numel() * ws.element_size(),
-                                                   _stream_handle(stream)))
+                                                   _nbytes(ws), _stream_handle(stream)))
 
     def close(self, stream=None):
         if getattr(self, "_ptr", None):
@@ -309,12 +384,15 @@ class Batch:
         """items: list of (plan, x [C, n] cuda float32, out tensor)."""
         self.items = list(items)
         self._arr = (_lib.BatchItem * max(1, len(self.items)))()
+        import torch
+        self.device = None
         for i, (plan, x, out) in enumerate(self.items):
-            if x.dtype.is_floating_point is False or not x.is_contiguous():
-                raise TypeError("x must be a contiguous float32 tensor")
-            if x.shape[-1] != plan.n:
-                raise ValueError("item %d: x has %d samples, plan expects %d" % (
-                    i, x.shape[-1], plan.n))
+            _check_dev("item %d x" % i, x, device=self.device, dtype=torch.float32)
+            self.device = x.device
+            if x.dim() != 2 or x.shape[1] != plan.n:
+                raise ValueError("item %d: x has shape %s, plan expects [C, %d]" % (
+                    i, tuple(x.shape), plan.n))
+            _check_dev("item %d out" % i, out, device=x.device, dtype=plan.out_dtype)
             if tuple(out.shape) != plan.output_shape(x.shape[0]):
                 raise ValueError("item %d: out must have shape %s" % (
                     i, plan.output_shape(x.shape[0])))
@@ -330,9 +408,9 @@ class Batch:
         return torch.empty(max(256, self.workspace_size()), dtype=torch.uint8, device=device)
 
     def execute(self, ws, stream=None):
+        _check_dev("ws", ws, device=self.device, min_bytes=self.workspace_size())
         _lib.check(self._lib.cwt_execute_batch(self._arr, len(self.items), _dptr(ws),
-                                               ws.numel() * ws.element_size(),
-                                               _stream_handle(stream)))
+                                               _nbytes(ws), _stream_handle(stream)))
 
 
 def cwt(x, sfreq, freqs, n_cycles, **kw):
