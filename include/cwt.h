@@ -221,6 +221,27 @@ int cwt_execute(const cwt_plan *plan, const float *x, int64_t C, void *out, void
                 size_t ws_bytes, void *stream);
 
 /*
+ * cwt_execute without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  The workspace (the
+ * channels' half spectra, cwt_workspace_size(plan, C) bytes) is a static
+ * device array of CWT_NOALLOC_SCRATCH_BYTES in the library, one copy per GPU,
+ * held until the process ends.  x, C, out and stream as for cwt_execute (the
+ * caller still owns x and out); results equal cwt_execute's bit for bit.
+ * Every call on one GPU shares that GPU's array: calls whose work overlaps on
+ * one GPU (on different streams, or from different threads without ordering)
+ * race on it and give wrong results; calls ordered on one stream are safe.
+ * The first call on a device looks up that device's array (the current
+ * device).  Calls no hipMalloc, hipFree or allocating routine.  Errors: those
+ * of cwt_execute, and CWT_E_UNSUPPORTED when cwt_workspace_size(plan, C)
+ * exceeds CWT_NOALLOC_SCRATCH_BYTES (nothing is launched; split C or use
+ * cwt_execute with a workspace).
+ */
+#define CWT_NOALLOC_SCRATCH_BYTES (16u << 20)
+int cwt_execute_noalloc(const cwt_plan *plan, const float *x, int64_t C, void *out,
+                        void *stream);
+
+/*
  * The two stages of cwt_execute, for callers that reuse the channel spectra
  * or time the stages separately.  cwt_forward_spectra writes the half
  * spectra X[c][b] = sum_{k<n} x[c][k] exp(-2 pi i b k / L), b <= L/2, of the

@@ -344,6 +344,19 @@ class Plan:
                 t.record_stream(stream)
         return out
 
+    def execute_noalloc(self, x, out, stream=None):
+        """execute() without a workspace and without any device allocation
+        (cwt_execute_noalloc): the workspace is the library's static device
+        scratch of CWT_NOALLOC_SCRATCH_BYTES per GPU, shared by every call on
+        that GPU, so calls that overlap on one GPU race.  x: cuda float32
+        [C, n] contiguous; out: preallocated, the plan's output dtype and
+        shape."""
+        C = self._check_x(x)
+        self._check_out(out, C, x.device)
+        _lib.check(self._lib.cwt_execute_noalloc(self._ptr, _dptr(x), C, _dptr(out),
+                                                 _stream_handle(stream)))
+        return out
+
     def forward_spectra(self, x, ws, stream=None):
         """Stage 1 of execute: channel half spectra into ws (cwt_forward_spectra)."""
         C = self._check_x(x)

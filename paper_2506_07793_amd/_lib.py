@@ -30,6 +30,8 @@ OUT = {"complex64": 0, "power": 1, "bandpower": 2}
 PRECISION = {"fp32": 0, "split_f16": 1, "split_bf16": 2}
 
 CWT_MAX_LEN = 20480
+#: bytes of the static device scratch cwt_execute_noalloc uses for its workspace
+CWT_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 
 class PlanOpts(ctypes.Structure):
@@ -126,6 +128,7 @@ SIGNATURES = {
     "cwt_plan_band_of_freq": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32)]),
     "cwt_workspace_size": (_SZ, [_VP, _I64]),
     "cwt_execute": (ctypes.c_int, [_VP, _VP, _I64, _VP, _VP, _SZ, _VP]),
+    "cwt_execute_noalloc": (ctypes.c_int, [_VP, _VP, _I64, _VP, _VP]),
     "cwt_forward_spectra": (ctypes.c_int, [_VP, _VP, _I64, _VP, _SZ, _VP]),
     "cwt_transform_spectra": (ctypes.c_int, [_VP, _I64, _VP, _VP, _SZ, _VP]),
     "cwt_plan_copy_tables": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float),

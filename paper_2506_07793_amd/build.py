@@ -16,7 +16,7 @@ LIB = os.path.join(OUT_DIR, "libcwt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["cwt_api.cpp", "cwt_kernels.hip", "cwt_fixed.hip", "cwt_split.hip", "cwt_stream_kernels.hip",
-           "cwt_pipeline.cpp", "cwt_user.cpp", "cwt_stream.cpp", "cwt_batch.cpp", "cwt_tune.cpp"]
+           "cwt_noalloc.hip", "cwt_pipeline.cpp", "cwt_user.cpp", "cwt_stream.cpp", "cwt_batch.cpp", "cwt_tune.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

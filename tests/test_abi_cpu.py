@@ -156,6 +156,7 @@ def test_validation_raw_abi():
     assert lib.cwt_plan_create(None, 10, 1000.0, fp, 1, None, 7.0, None, None) == _lib.CWT_E_INVALID
     # execute with NULL plan / destroy NULL
     assert lib.cwt_execute(None, None, 1, None, None, 0, None) == _lib.CWT_E_INVALID
+    assert lib.cwt_execute_noalloc(None, None, 1, None, None) == _lib.CWT_E_INVALID
     assert lib.cwt_plan_destroy(None, None) == _lib.CWT_OK
     assert lib.cwt_workspace_size(None, 4) == 0
     # per-launch timing: NULL plan rejected
@@ -312,3 +313,23 @@ def test_product_package_does_not_use_the_oracle():
                 if "oracle" in text or "orc_" in text:
                     hits.append(fn)
     assert not hits, hits
+
+
+def test_noalloc_source_makes_no_allocating_call():
+    """cwt_execute_noalloc's source holds the static scratch array and resolves
+    its device address with hipGetSymbolAddress; it calls no allocator, frees
+    nothing, never hands the array's host-side name to a kernel or copy, and
+    routes through no torch code."""
+    import os
+    import re
+    src = open(os.path.join(os.path.dirname(cwt.__file__), "csrc", "cwt_noalloc.hip")).read()
+    code = re.sub(r"//[^\n]*", "", src)
+    assert re.search(r"static __device__ __align__\(256\) unsigned char scratch\[", code)
+    assert "hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))" in code
+    for bad in ("hipMalloc", "hipFree", "hipHostMalloc", "hipMemset", "malloc(", "new ",
+                "torch", "hipMemcpy"):
+        assert bad not in code, bad
+    # outside string literals, the only uses of the name are the definition
+    # and the symbol lookup
+    bare = re.sub(r'"(?:[^"\\\n]|\\.)*"', '""', code)
+    assert len(re.findall(r"\bscratch\b", bare)) == 2
