@@ -279,6 +279,12 @@ __device__ __forceinline__ void fixed_main_row(const MainParams &p, int item)
     const cf *X = reinterpret_cast<const cf *>(p.Xh) + (int64_t)c * p.Lh;
     float *orow_band = reinterpret_cast<float *>(p.out) + ((int64_t)c * p.n_rows + row) * N;
     const float inv_n = 1.0f / (float)(qe - qb);
+    // Band power: thread t owns samples t + T m of every frequency's
+    // transform, so the sum over the band's frequencies stays in registers
+    // and the row is stored once.
+    float acc[kV];
+#pragma unroll
+    for (int m = 0; m < kV; ++m) acc[m] = 0.f;
 
     for (int q = qb; q < qe; ++q) {
         const int f = (MODE == kOutBand) ? p.grp_freq[q] : q;
@@ -318,21 +324,20 @@ __device__ __forceinline__ void fixed_main_row(const MainParams &p, int item)
             run_passes<1, L, 1, TWM>(v, t, tw, lds, RL{});
         }
         // epilogue: v[m] is sample t + T m
+        if (MODE == kOutBand) {
+#pragma unroll
+            for (int m = 0; m < kV; ++m) acc[m] += v[m].x * v[m].x + v[m].y * v[m].y;
+            continue;
+        }
         float2 *ocx = reinterpret_cast<float2 *>(p.out) + ((int64_t)c * p.n_rows + f) * N;
         float *opw = reinterpret_cast<float *>(p.out) + ((int64_t)c * p.n_rows + f) * N;
-        const bool first = (q == qb), final_f = (q == qe - 1);
         auto store = [&](int m) {
             const int ts = t + T * m;
             const cf w = v[m];
-            const float pw = w.x * w.x + w.y * w.y;
-            if (MODE == kOutComplex) {
+            if (MODE == kOutComplex)
                 *reinterpret_cast<f2v *>(ocx + ts) = f2v{w.x, w.y};
-            } else if (MODE == kOutPower) {
-                opw[ts] = pw;
-            } else {
-                float a = first ? pw : orow_band[ts] + pw;
-                orow_band[ts] = final_f ? a * inv_n : a;
-            }
+            else
+                opw[ts] = w.x * w.x + w.y * w.y;
         };
         if (N == L) {
             // whole rows (uniform branch): no per-sample bounds test
@@ -343,6 +348,11 @@ __device__ __forceinline__ void fixed_main_row(const MainParams &p, int item)
             for (int m = 0; m < kV; ++m)
                 if (t + T * m < N) store(m);
         }
+    }
+    if (MODE == kOutBand) {
+#pragma unroll
+        for (int m = 0; m < kV; ++m)
+            if (N == L || t + T * m < N) orow_band[t + T * m] = acc[m] * inv_n;
     }
 }
 

@@ -126,6 +126,15 @@ __global__ void __launch_bounds__(kT, 4) k_split_main(MainParams p)
     const cf *X = reinterpret_cast<const cf *>(p.Xh) + (int64_t)c * p.Lh;
     float *orow_band = reinterpret_cast<float *>(p.out) + ((int64_t)c * p.n_rows + row) * N;
     const float inv_n = 1.0f / (float)(qe - qb);
+    // Band power: each lane owns the same 16 output samples of every
+    // frequency's transform (slot j + 256 k of the last stage), so the sum
+    // over the band's frequencies stays in registers and the row is stored
+    // once.
+    float acc[4][4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[g][i] = 0.f;
 
     for (int qq = qb; qq < qe; ++qq) {
         const int f = (MODE == kOutBand) ? p.grp_freq[qq] : qq;
@@ -135,7 +144,6 @@ __global__ void __launch_bounds__(kT, 4) k_split_main(MainParams p)
         const int lo_u = bd.lo < 0 ? bd.lo + kL : bd.lo;
         float2 *ocx = reinterpret_cast<float2 *>(p.out) + ((int64_t)c * p.n_rows + f) * N;
         float *opw = reinterpret_cast<float *>(p.out) + ((int64_t)c * p.n_rows + f) * N;
-        const bool first = (qq == qb), final_f = (qq == qe - 1);
         if (qq != qb) __syncthreads();
 
         // A band of at most L/16 bins leaves one nonzero input in each
@@ -237,21 +245,28 @@ __global__ void __launch_bounds__(kT, 4) k_split_main(MainParams p)
                         const int jn = d & 255, rn = d >> 8;
                         y = mul(y, tw[(jn & (Nn - 1)) * rn * (kL / (Nn * 16))]);
                         lds[d] = y;
+                    } else if (MODE == kOutBand) {
+                        acc[g][i] += y.x * y.x + y.y * y.y;
                     } else if (d < N) {
-                        const float pw = y.x * y.x + y.y * y.y;
-                        if (MODE == kOutComplex) {
+                        if (MODE == kOutComplex)
                             ocx[d] = make_float2(y.x, y.y);
-                        } else if (MODE == kOutPower) {
-                            opw[d] = pw;
-                        } else {
-                            const float a = first ? pw : orow_band[d] + pw;
-                            orow_band[d] = final_f ? a * inv_n : a;
-                        }
+                        else
+                            opw[d] = y.x * y.x + y.y * y.y;
                     }
                 }
             }
             if (s < 2) __syncthreads();
         }
+    }
+    if (MODE == kOutBand) {
+        // last-stage slot of (g, i): j + 256 k with j = 64 wave + 16 g + n < 256
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int d = 64 * wave + 16 * g + n + 256 * (4 * q + i);
+                if (d < N) orow_band[d] = acc[g][i] * inv_n;
+            }
     }
 }
 
