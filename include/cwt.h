@@ -72,6 +72,25 @@ enum cwt_precision {
     CWT_PREC_SPLIT_BF16 = 2  /* DFT-as-GEMM radix stages on BF16 MFMA, hi+lo split  */
 };
 
+/* ---- device memory --------------------------------------------------- */
+/*
+ * Device memory the library owns (plan tables, a plan's own workspace,
+ * stream-session rings and batch buffers) comes from the caller's allocator
+ * when one is given, e.g. a framework's caching allocator.
+ *   alloc(bytes, stream, ctx): return device memory of at least `bytes`
+ *     bytes, usable by work enqueued on `stream` after the call (stream-
+ *     ordered allocation), or NULL on failure (the library then returns
+ *     CWT_E_NOMEM).
+ *   free(ptr, bytes, stream, ctx): give back a block alloc returned; the
+ *     memory must not be reused by anything before the work already enqueued
+ *     on `stream` has finished (stream-ordered free).
+ * Without callbacks the library uses HIP's stream-ordered pool allocator
+ * (hipMallocAsync / hipFreeAsync on the same streams).  Neither path
+ * synchronises the host.
+ */
+typedef void *(*cwt_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*cwt_free_fn)(void *ptr, size_t bytes, void *stream, void *ctx);
+
 /* Largest padded length one workgroup holds in LDS (complex64, 160 KB). */
 #define CWT_MAX_LEN 20480
 #define CWT_MAX_FREQS 4096
@@ -91,6 +110,14 @@ typedef struct cwt_plan_opts {
                                  beta 13-30, gamma 30-100 Hz.  Copied at create. */
     double gmw_beta;          /* GMW beta (default 17.5, the paper's value)        */
     double gmw_gamma;         /* GMW gamma (default 3)                             */
+    int64_t max_channels;     /* 0 (default): no limit.  > 0: execute calls take at
+                                 most this many channels, and the plan owns a
+                                 workspace for that many, used when ws is NULL   */
+    cwt_alloc_fn alloc;       /* device allocator of the plan's memory, or NULL
+                                 (HIP's stream-ordered pool); alloc and free are
+                                 given together or not at all                    */
+    cwt_free_fn free;
+    void *alloc_ctx;          /* passed to alloc and free                        */
 } cwt_plan_opts;
 
 /* Fill *opts with the defaults: Morlet, SMOOTH7, complex64, FP32, default bands,
@@ -120,11 +147,17 @@ typedef struct cwt_plan cwt_plan;
  * On success the plan owns device memory for the wavelet spectra (FP64
  * evaluation on the GPU, rounded once to FP32, 1/L folded in, only the bins
  * whose magnitude is at least 1e-12 of the peak) and the twiddle table
- * exp(2 pi i m / L) (FP64 on the GPU, rounded once).  Their generation is
- * enqueued on `stream`; the plan may be used on any stream once `stream` has
- * reached that point (cwt_plan_create does not synchronise).  The spectra
- * are the Fourier-domain wavelets of section "Fourier transformed formula"
- * (Morlet, Gabor, GMW equations), sampled on the DFT bins.
+ * exp(2 pi i m / L) (FP64 on the GPU, rounded once), and with max_channels a
+ * workspace; all of it comes from opts->alloc on `stream` (or HIP's
+ * stream-ordered pool), so the spectra and tables are made in GPU memory,
+ * where the data they are applied to stays (section "Optimizing
+ * performance").  Their generation is enqueued on `stream`; the plan may be
+ * used on any stream once `stream` has reached that point (cwt_plan_create
+ * does not synchronise; the stream server and cwt_execute_batch wait for it
+ * themselves).  The spectra are the Fourier-domain wavelets of section
+ * "Fourier transformed formula" (Morlet, Gabor, GMW equations), sampled on
+ * the DFT bins.  Errors also include CWT_E_INVALID for max_channels < 0 or
+ * only one of alloc / free, and CWT_E_NOMEM when an allocation fails.
  *
  * Environment, read when a plan is created: CWT_GENERIC_ONLY=1 makes
  * power-of-two lengths use the runtime-radix kernel instead of the
@@ -156,6 +189,8 @@ typedef struct cwt_plan_desc {
     int32_t kernel;          /* 0 generic runtime-radix kernel, 1 register-resident
                                 kernel specialised for this padded length          */
     int32_t spectrum_complex;/* 1: stored spectra are complex (sampled wavelets)  */
+    int64_t max_channels;    /* opts->max_channels (0: no limit)                   */
+    int64_t device_bytes;    /* device memory the plan owns (0 before creation)   */
 } cwt_plan_desc;
 
 int cwt_plan_info(const cwt_plan *plan, cwt_plan_desc *desc);
@@ -208,12 +243,15 @@ size_t cwt_workspace_size(const cwt_plan *plan, int64_t C);
  * Transform C channels.  x: device float32 [C][n] row-major.  out: device
  * [C][n_freqs][n] complex64 (interleaved re, im) or float32 power, or
  * [C][n_bands][n] float32 band power, fully overwritten.  ws: device
- * workspace of at least cwt_workspace_size(plan, C) bytes, 256-byte aligned.
- * x, out and ws must not overlap.  Asynchronous on `stream`; the plan may be
- * executed concurrently on several streams, each with its own ws and out.
- * C == 0 is a no-op.  Errors: CWT_E_INVALID for NULL or misaligned pointers
- * (x 4-byte, out 8-byte, ws 256-byte aligned), C outside [0, 2^24] or a
- * workspace too small; CWT_E_UNSUPPORTED when one launch would hold 2^32
+ * workspace of at least cwt_workspace_size(plan, C) bytes, 256-byte aligned,
+ * or NULL (with ws_bytes 0) to use the workspace of a plan created with
+ * max_channels >= C; calls on one plan that share its own workspace must be
+ * ordered on one stream.  x, out and ws must not overlap.  Asynchronous on
+ * `stream`; the plan may be executed concurrently on several streams, each
+ * with its own ws and out.  C == 0 is a no-op.  Errors: CWT_E_INVALID for
+ * NULL or misaligned pointers (x 4-byte, out 8-byte, ws 256-byte aligned), C
+ * outside [0, 2^24], C above the plan's max_channels, a NULL ws on a plan
+ * without one, or a workspace too small; CWT_E_UNSUPPORTED when one launch would hold 2^32
  * work-items or more (one workgroup of cwt_plan_desc.threads per output row
  * of each channel, at most 1024 threads): split the channels over calls.
  */
@@ -390,19 +428,30 @@ int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *ws, size_t w
  * "Discussion"): sessions push samples, and for every completed hop the
  * server transforms the sliding window of the last n samples (the plan's n)
  * and reports, per channel and band, the band power averaged over the hop's
- * trailing samples of the window's transform.  A worker thread batches the
- * hops of many sessions into one set of launches (up to max_batch sessions,
+ * trailing samples of the window's transform.  A launcher thread batches the
+ * hops of many sessions into one set of launches (up to max_batch hops,
  * launched when the oldest pending hop has waited deadline_us or the batch
- * is full) and stamps the completion time of each result.
+ * is full; one session's hops in order, at most max_session_windows of its
+ * window hops per launch), and a completion thread stamps the completion
+ * time of each result; the next batch is enqueued while the previous one
+ * completes (two batches of a session class in flight).
  */
 typedef struct cwt_server cwt_server;
 typedef struct cwt_session cwt_session;
 
 typedef struct cwt_server_opts {
-    int32_t max_batch;        /* sessions per launch (default 256)                   */
+    int32_t max_batch;        /* hops per launch (default 256)                       */
     int32_t deadline_us;      /* longest wait of a pending hop before launch (500)   */
-    int32_t max_pending;      /* queued hops per session before CWT_E_AGAIN (64)     */
-    int32_t reserved_;
+    int32_t max_pending;      /* queued window hops per session before CWT_E_AGAIN
+                                 (64); hops before the first full window only fill
+                                 the ring and are not counted                        */
+    int32_t max_session_windows; /* K: window-producing hops of one session in one
+                                 launch (default 4, at most 64); each ring holds
+                                 n + (K - 1) hop samples per channel               */
+    cwt_alloc_fn alloc;       /* device allocator of rings and batch buffers, or
+                                 NULL (HIP's stream-ordered pool); with free       */
+    cwt_free_fn free;
+    void *alloc_ctx;
 } cwt_server_opts;
 
 typedef struct cwt_server_stats {
@@ -418,9 +467,16 @@ typedef struct cwt_server_stats {
 int cwt_server_opts_init(cwt_server_opts *opts);
 
 /* Create a server that may hold at most hbm_budget_bytes of device memory
- * for session rings and batch workspaces.  It owns a non-blocking HIP stream
- * of default priority and a worker thread.  opts may be NULL (defaults). */
-int cwt_server_create(cwt_server **out, size_t hbm_budget_bytes, const cwt_server_opts *opts);
+ * for session rings and batch workspaces, allocated and freed through
+ * opts->alloc / opts->free (or HIP's stream-ordered pool) on the server's
+ * stream.  Every device operation of the server (allocation, ring clearing,
+ * copies, launches, frees) is enqueued on `stream`, which the caller owns and
+ * must keep alive until cwt_server_destroy returns; NULL makes the server
+ * create (and later destroy) its own non-blocking stream of default priority.
+ * The server runs a worker thread.  opts may be NULL (defaults).  Errors:
+ * CWT_E_INVALID for bad options or only one of alloc / free. */
+int cwt_server_create(cwt_server **out, size_t hbm_budget_bytes, const cwt_server_opts *opts,
+                      void *stream);
 
 /* Stop the worker (pending hops are processed first), free everything.
  * Sessions still open are closed. */
@@ -428,10 +484,14 @@ int cwt_server_destroy(cwt_server *srv);
 
 /* Open a session of C channels on `plan` (which must use CWT_OUT_BANDPOWER_F32;
  * its n is the window length W) with hop samples per result, 1 <= hop <= W.
- * The ring holds zeros until the first W samples have arrived; no result is
- * produced before that.  Returns CWT_E_BUDGET when the session's ring plus
- * (for a new (plan, C, hop) class) the class's batch workspace would exceed
- * the server's budget.  The plan must outlive the session. */
+ * The session's device ring (W + (K - 1) hop samples per channel, K =
+ * max_session_windows) is allocated and cleared in stream order on the
+ * server's stream, and the server's stream waits for the plan's tables if
+ * they are still being written; the call does not wait for the device.  No
+ * result is produced before the first W samples have arrived.  Returns
+ * CWT_E_BUDGET when the session's ring plus (for a new (plan, C, hop) class)
+ * the class's batch buffers would exceed the server's budget.  The plan must
+ * outlive the session. */
 int cwt_stream_open(cwt_server *srv, const cwt_plan *plan, int64_t C, int64_t hop,
                     cwt_session **out);
 
@@ -452,7 +512,9 @@ int cwt_stream_poll(cwt_session *s, float *bp, uint64_t *hop_idx, uint64_t *t_pu
 /* Block until every hop queued so far on the server has been processed. */
 int cwt_server_flush(cwt_server *srv);
 
-/* Close a session (its queued hops are dropped) and release its ring. */
+/* Close a session: its queued hops are dropped, hops already launched are
+ * waited for (their results are discarded), and its ring is freed in stream
+ * order on the server's stream. */
 int cwt_stream_close(cwt_session *s);
 
 int cwt_server_get_stats(const cwt_server *srv, cwt_server_stats *stats);
@@ -460,9 +522,12 @@ int cwt_server_get_stats(const cwt_server *srv, cwt_server_stats *stats);
 /* CLOCK_MONOTONIC in nanoseconds (the clock of the stream time stamps). */
 uint64_t cwt_now_ns(void);
 
-/* Release the plan.  Synchronises `stream` first, so work already enqueued
- * on it that uses the plan completes before the tables are freed; work on
- * other streams that uses the plan must be complete before this call. */
+/* Release the plan.  Its device memory is freed in stream order on `stream`
+ * (opts->free, or hipFreeAsync): work already enqueued on `stream` that uses
+ * the plan finishes before the memory can be reused, and the call does not
+ * wait for it.  Work on other streams that uses the plan must be ordered
+ * before `stream`'s current point (an event, or a synchronisation) first.
+ * The host-side plan object is gone when the call returns. */
 int cwt_plan_destroy(cwt_plan *plan, void *stream);
 
 /* Thread-local description of the last error on this thread ("" if none). */

@@ -63,6 +63,64 @@ def _on_other_stream(stream):
     return stream is not None and stream != torch.cuda.current_stream()
 
 
+class TorchDeviceMemory:
+    """Device-memory callbacks (cwt_alloc_fn / cwt_free_fn) served by torch's
+    caching allocator, so that the library's own buffers (plan tables, a
+    plan's workspace, stream rings) come from torch like the caller's tensors.
+
+    alloc(bytes, stream) returns the storage of a uint8 tensor allocated on
+    `stream` (torch's allocator then orders its reuse on that stream); free
+    releases it, first marking it as used by the freeing stream when that is
+    another one, so torch does not hand the memory out again before the work
+    already enqueued there has finished (stream-ordered free).  Counts every
+    byte that goes out and comes back."""
+
+    def __init__(self, device=None):
+        import torch
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        self._blocks = {}
+        self.bytes_out = 0
+        self.bytes_back = 0
+        self.alloc_fn = _lib.ALLOC_FN(self._alloc)
+        self.free_fn = _lib.FREE_FN(self._free)
+
+    def _torch_stream(self, handle):
+        import torch
+        if not handle:
+            return torch.cuda.default_stream(self.device)
+        return torch.cuda.ExternalStream(handle, device=self.device)
+
+    def _alloc(self, nbytes, stream, ctx):
+        import torch
+        try:
+            with torch.cuda.stream(self._torch_stream(stream)):
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        except Exception:  # the library reports CWT_E_NOMEM
+            return None
+        ptr = t.data_ptr()
+        self._blocks[ptr] = (t, int(stream or 0), int(nbytes))
+        self.bytes_out += int(nbytes)
+        return ptr
+
+    def _free(self, ptr, nbytes, stream, ctx):
+        t, s_alloc, n = self._blocks.pop(int(ptr))
+        if int(stream or 0) != s_alloc:
+            t.record_stream(self._torch_stream(stream))
+        self.bytes_back += n
+        del t
+
+    @property
+    def outstanding(self):
+        """Bytes handed out and not yet given back."""
+        return self.bytes_out - self.bytes_back
+
+    def fill(self, opts):
+        opts.alloc = self.alloc_fn
+        opts.free = self.free_fn
+        opts.alloc_ctx = None
+
+
 def _make_opts(lib, wavelet, pad, explicit_len, out, precision, bands, gmw_beta=17.5,
                gmw_gamma=3.0):
     opts = _lib.PlanOpts()
@@ -123,12 +181,20 @@ class Plan:
 
     def __init__(self, n, sfreq, freqs, n_cycles=None, omega0=None, wavelet="morlet",
                  pad="smooth7", explicit_len=0, out="complex64", precision="fp32", bands=None,
-                 stream=None, gmw_beta=17.5, gmw_gamma=3.0):
+                 stream=None, gmw_beta=17.5, gmw_gamma=3.0, max_channels=0, memory="torch"):
+        """memory: "torch" (the plan's device memory from torch's caching
+        allocator, the default), a TorchDeviceMemory, or None (HIP's
+        stream-ordered pool).  max_channels > 0 gives the plan its own
+        workspace for that many channels (execute without ws uses it)."""
         lib = _lib.load()
         self._lib = lib
         self.freqs = np.ascontiguousarray(np.asarray(freqs, dtype=np.float64).ravel())
         opts, self._edges = _make_opts(lib, wavelet, pad, explicit_len, out, precision, bands,
                                        gmw_beta, gmw_gamma)
+        opts.max_channels = int(max_channels)
+        self.memory = TorchDeviceMemory() if memory == "torch" else memory
+        if self.memory is not None:
+            self.memory.fill(opts)
         self._cyc, cyc_ptr, om = _cycles(self.freqs, n_cycles, omega0, wavelet)
         handle = ctypes.c_void_p()
         self._ptr = None
@@ -140,7 +206,8 @@ class Plan:
 
     @classmethod
     def from_wavelets(cls, n, sfreq, freqs, wavelets, pad="smooth7", explicit_len=0,
-                      out="complex64", bands=None, stream=None):
+                      out="complex64", bands=None, stream=None, max_channels=0,
+                      memory="torch"):
         """Plan from sampled time-domain wavelets (cwt_plan_create_from_wavelets):
         wavelets [n_freqs, w_len] complex, sample j at time (j - w_len // 2) / sfreq,
         used as given; freqs label the rows (band grouping)."""
@@ -152,6 +219,10 @@ class Plan:
         if wv.shape[0] != len(self.freqs):
             raise ValueError("one wavelet per frequency")
         opts, self._edges = _make_opts(lib, "morlet", pad, explicit_len, out, "fp32", bands)
+        opts.max_channels = int(max_channels)
+        self.memory = TorchDeviceMemory() if memory == "torch" else memory
+        if self.memory is not None:
+            self.memory.fill(opts)
         self._cyc = None
         handle = ctypes.c_void_p()
         self._ptr = None
@@ -333,6 +404,14 @@ class Plan:
         if out is None:
             out = self.alloc_output(C, device=x.device)
         self._check_out(out, C, x.device)
+        if ws is None and 0 < C <= int(self.desc.max_channels):
+            # the plan's own workspace (calls using it are ordered on one stream)
+            _lib.check(self._lib.cwt_execute(self._ptr, _dptr(x), C, _dptr(out), None, 0,
+                                             _stream_handle(stream)))
+            if other:
+                for t in made:
+                    t.record_stream(stream)
+            return out
         if ws is None:
             ws = self.alloc_workspace(C, device=x.device)
             made.append(ws)

@@ -34,6 +34,12 @@ CWT_MAX_LEN = 20480
 CWT_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 
+#: cwt_alloc_fn / cwt_free_fn: device memory callbacks (include/cwt.h)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                           ctypes.c_void_p)
+
+
 class PlanOpts(ctypes.Structure):
     _fields_ = [
         ("wavelet", ctypes.c_int32),
@@ -45,6 +51,10 @@ class PlanOpts(ctypes.Structure):
         ("band_edges", ctypes.POINTER(ctypes.c_double)),
         ("gmw_beta", ctypes.c_double),
         ("gmw_gamma", ctypes.c_double),
+        ("max_channels", ctypes.c_int64),
+        ("alloc", ALLOC_FN),
+        ("free", FREE_FN),
+        ("alloc_ctx", ctypes.c_void_p),
     ]
 
 
@@ -66,6 +76,8 @@ class PlanDesc(ctypes.Structure):
         ("max_band_bins", ctypes.c_int64),
         ("kernel", ctypes.c_int32),
         ("spectrum_complex", ctypes.c_int32),
+        ("max_channels", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64),
     ]
 
 
@@ -74,7 +86,10 @@ class ServerOpts(ctypes.Structure):
         ("max_batch", ctypes.c_int32),
         ("deadline_us", ctypes.c_int32),
         ("max_pending", ctypes.c_int32),
-        ("reserved_", ctypes.c_int32),
+        ("max_session_windows", ctypes.c_int32),
+        ("alloc", ALLOC_FN),
+        ("free", FREE_FN),
+        ("alloc_ctx", ctypes.c_void_p),
     ]
 
 
@@ -148,7 +163,8 @@ SIGNATURES = {
     "cwt_batch_workspace_size": (_SZ, [ctypes.POINTER(BatchItem), _I32]),
     "cwt_execute_batch": (ctypes.c_int, [ctypes.POINTER(BatchItem), _I32, _VP, _SZ, _VP]),
     "cwt_server_opts_init": (ctypes.c_int, [ctypes.POINTER(ServerOpts)]),
-    "cwt_server_create": (ctypes.c_int, [ctypes.POINTER(_VP), _SZ, ctypes.POINTER(ServerOpts)]),
+    "cwt_server_create": (ctypes.c_int, [ctypes.POINTER(_VP), _SZ, ctypes.POINTER(ServerOpts),
+                                         _VP]),
     "cwt_server_destroy": (ctypes.c_int, [_VP]),
     "cwt_stream_open": (ctypes.c_int, [_VP, _VP, _I64, _I64, ctypes.POINTER(_VP)]),
     "cwt_stream_push": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_float), _I64, ctypes.c_uint64]),

@@ -307,6 +307,16 @@ int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
         return fail(CWT_E_INVALID, "unknown output mode %d", o.out);
     if (o.precision < CWT_PREC_FP32 || o.precision > CWT_PREC_SPLIT_BF16)
         return fail(CWT_E_INVALID, "unknown precision %d", o.precision);
+    if (o.max_channels < 0 || o.max_channels > ((int64_t)1 << 24))
+        return fail(CWT_E_INVALID, "max_channels must be in [0, 2^24] (got %lld)",
+                    (long long)o.max_channels);
+    {
+        const DevMem m{o.alloc, o.free, o.alloc_ctx};
+        int rc = check_dev_mem(m);
+        if (rc != CWT_OK) return rc;
+        P.mem = m;
+    }
+    P.max_channels = o.max_channels;
     if (o.pad == CWT_PAD_EXPLICIT && o.explicit_len < n)
         return fail(CWT_E_INVALID, "explicit_len %lld < n %lld", (long long)o.explicit_len,
                     (long long)n);
@@ -436,30 +446,31 @@ int check_device(int *dev_out)
 }
 
 template <class T>
-static int dev_upload(T **dst, const T *src, size_t count, hipStream_t s, const char *what)
+static int dev_upload(cwt_plan &P, T **dst, const T *src, size_t count, hipStream_t s,
+                      const char *what)
 {
     *dst = nullptr;
     if (count == 0) return CWT_OK;
-    hipError_t e = hipMalloc((void **)dst, count * sizeof(T));
-    if (e != hipSuccess) {
+    int rc = plan_alloc(P, (void **)dst, count * sizeof(T), s, what);
+    if (rc != CWT_OK) {
         *dst = nullptr;
-        return fail(CWT_E_NOMEM, "hipMalloc(%s, %zu bytes) failed: %s", what, count * sizeof(T),
-                    hipGetErrorName(e));
+        return rc;
     }
     if (src) {
-        e = hipMemcpyAsync(*dst, src, count * sizeof(T), hipMemcpyHostToDevice, s);
+        hipError_t e = hipMemcpyAsync(*dst, src, count * sizeof(T), hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
         // src is owned by the plan and outlives the copy.
     }
     return CWT_OK;
 }
 
-void free_plan_device(cwt_plan &P)
+void free_plan_device(cwt_plan &P, hipStream_t s)
 {
-    void *ptrs[] = {P.d_freqs, P.d_sigmas, P.d_band, P.d_H, P.d_Hc, P.d_tw, P.d_grp_freq,
-                    P.d_grp_off};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+    plan_free_all(P, s);
+    if (P.ready) (void)hipEventDestroy(P.ready);
+    P.ready = nullptr;
+    P.own_ws = nullptr;
+    P.own_ws_bytes = 0;
     P.d_freqs = P.d_sigmas = nullptr;
     P.d_band = nullptr;
     P.d_H = nullptr;
@@ -471,16 +482,19 @@ void free_plan_device(cwt_plan &P)
 int upload_plan(cwt_plan &P, hipStream_t s)
 {
     int rc;
-    if ((rc = dev_upload(&P.d_freqs, P.freqs.data(), P.freqs.size(), s, "freqs"))) return rc;
-    if ((rc = dev_upload(&P.d_sigmas, P.sigmas.data(), P.sigmas.size(), s, "sigmas"))) return rc;
-    if ((rc = dev_upload(&P.d_band, P.bands.data(), P.bands.size(), s, "bands"))) return rc;
-    if ((rc = dev_upload<float>(&P.d_H, nullptr, std::max<int64_t>(P.total_bins, 1), s, "H")))
+    if ((rc = dev_upload(P, &P.d_freqs, P.freqs.data(), P.freqs.size(), s, "freqs"))) return rc;
+    if ((rc = dev_upload(P, &P.d_sigmas, P.sigmas.data(), P.sigmas.size(), s, "sigmas")))
         return rc;
-    if ((rc = dev_upload<float2>(&P.d_tw, nullptr, P.L, s, "twiddles"))) return rc;
+    if ((rc = dev_upload(P, &P.d_band, P.bands.data(), P.bands.size(), s, "bands"))) return rc;
+    if ((rc = dev_upload<float>(P, &P.d_H, nullptr, std::max<int64_t>(P.total_bins, 1), s, "H")))
+        return rc;
+    if ((rc = dev_upload<float2>(P, &P.d_tw, nullptr, P.L, s, "twiddles"))) return rc;
     if (P.n_bands > 0) {
-        if ((rc = dev_upload(&P.d_grp_freq, P.grp_freq.data(), P.grp_freq.size(), s, "groups")))
+        if ((rc = dev_upload(P, &P.d_grp_freq, P.grp_freq.data(), P.grp_freq.size(), s,
+                             "groups")))
             return rc;
-        if ((rc = dev_upload(&P.d_grp_off, P.grp_off.data(), P.grp_off.size(), s, "group offs")))
+        if ((rc = dev_upload(P, &P.d_grp_off, P.grp_off.data(), P.grp_off.size(), s,
+                             "group offs")))
             return rc;
     }
     GenParams g{};
@@ -497,6 +511,31 @@ int upload_plan(cwt_plan &P, hipStream_t s)
     g.tw = P.d_tw;
     hipError_t e = launch_generate(g, P.max_bins, s);
     if (e != hipSuccess) return hip_fail(e, "generator launch");
+    return CWT_OK;
+}
+
+int finish_plan(cwt_plan &P, hipStream_t s)
+{
+    if (P.max_channels > 0) {
+        const size_t b = cwt_workspace_size(&P, P.max_channels);
+        int rc = plan_alloc(P, &P.own_ws, b, s, "plan workspace");
+        if (rc != CWT_OK) return rc;
+        P.own_ws_bytes = b;
+    }
+    hipError_t e = hipEventCreateWithFlags(&P.ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(P.ready, s);
+    if (e != hipSuccess) return hip_fail(e, "plan ready event");
+    return CWT_OK;
+}
+
+int wait_plan_ready(const cwt_plan &P, hipStream_t s)
+{
+    if (!P.ready) return CWT_OK;
+    hipError_t e = hipEventQuery(P.ready);
+    if (e == hipSuccess) return CWT_OK;  // tables already written
+    if (e != hipErrorNotReady) return hip_fail(e, "hipEventQuery(plan ready)");
+    e = hipStreamWaitEvent(s, P.ready, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent(plan ready)");
     return CWT_OK;
 }
 
@@ -588,8 +627,9 @@ extern "C" int cwt_plan_create(cwt_plan **out, int64_t n, double sfreq, const do
     if (rc == CWT_OK) rc = upload_plan(*P, (hipStream_t)stream);
     if (rc == CWT_OK && P->opts.precision != CWT_PREC_FP32)
         rc = prepare_split_precision(*P, (hipStream_t)stream);
+    if (rc == CWT_OK) rc = finish_plan(*P, (hipStream_t)stream);
     if (rc != CWT_OK) {
-        free_plan_device(*P);
+        free_plan_device(*P, (hipStream_t)stream);
         delete P;
         return rc;
     }
@@ -616,6 +656,10 @@ static void fill_desc(const cwt_plan *P, cwt_plan_desc *d)
     d->max_band_bins = P->max_bins;
     d->kernel = P->use_fixed ? 1 : 0;
     d->spectrum_complex = P->user ? 1 : 0;
+    d->max_channels = P->max_channels;
+    size_t bytes = 0;
+    for (const auto &b : P->blocks) bytes += b.n;
+    d->device_bytes = (int64_t)bytes;
 }
 
 extern "C" int cwt_plan_info(const cwt_plan *P, cwt_plan_desc *d)
@@ -659,8 +703,14 @@ int check_exec_args(const cwt_plan *P, const float *x, bool x_needed, int64_t C,
     if (!P) return fail(CWT_E_INVALID, "plan is NULL");
     if (C < 0 || C > (int64_t)1 << 24) return fail(CWT_E_INVALID, "C out of range");
     if (C == 0) return CWT_OK;
-    if ((x_needed && !x) || (out_needed && !out) || !ws)
+    if (P->max_channels > 0 && C > P->max_channels)
+        return fail(CWT_E_INVALID, "C = %lld exceeds the plan's max_channels %lld", (long long)C,
+                    (long long)P->max_channels);
+    if ((x_needed && !x) || (out_needed && !out))
         return fail(CWT_E_INVALID, "NULL device pointer");
+    if (!ws)
+        return fail(CWT_E_INVALID, "ws is NULL and the plan has no workspace of its own "
+                                   "(create it with max_channels)");
     if (((uintptr_t)ws & 255) != 0) return fail(CWT_E_INVALID, "ws must be 256-byte aligned");
     if ((x_needed && ((uintptr_t)x & 3) != 0) || (out_needed && ((uintptr_t)out & 7) != 0))
         return fail(CWT_E_INVALID, "x must be 4-byte and out 8-byte aligned");
@@ -682,10 +732,20 @@ int check_exec_args(const cwt_plan *P, const float *x, bool x_needed, int64_t C,
     return CWT_OK;
 }
 
+// A NULL workspace means the plan's own (plans created with max_channels).
+static void resolve_ws(const cwt_plan *P, void *&ws, size_t &ws_bytes)
+{
+    if (P && !ws && ws_bytes == 0 && P->own_ws) {
+        ws = P->own_ws;
+        ws_bytes = P->own_ws_bytes;
+    }
+}
+
 extern "C" int cwt_execute(const cwt_plan *P, const float *x, int64_t C, void *out, void *ws,
                            size_t ws_bytes, void *stream)
 {
     clear_error();
+    resolve_ws(P, ws, ws_bytes);
     int rc = check_exec_args(P, x, true, C, out, true, ws, ws_bytes);
     if (rc != CWT_OK || C == 0) return rc;
     if (P->opts.precision != CWT_PREC_FP32)
@@ -697,6 +757,7 @@ extern "C" int cwt_forward_spectra(const cwt_plan *P, const float *x, int64_t C,
                                    size_t ws_bytes, void *stream)
 {
     clear_error();
+    resolve_ws(P, ws, ws_bytes);
     int rc = check_exec_args(P, x, true, C, nullptr, false, ws, ws_bytes);
     if (rc != CWT_OK || C == 0) return rc;
     return enqueue_forward(*P, x, C, P->n, ws, (hipStream_t)stream);
@@ -706,6 +767,7 @@ extern "C" int cwt_transform_spectra(const cwt_plan *P, int64_t C, void *out, vo
                                      size_t ws_bytes, void *stream)
 {
     clear_error();
+    resolve_ws(P, ws, ws_bytes);
     int rc = check_exec_args(P, nullptr, false, C, out, true, ws, ws_bytes);
     if (rc != CWT_OK || C == 0) return rc;
     if (P->opts.precision != CWT_PREC_FP32)
@@ -791,11 +853,12 @@ extern "C" int cwt_plan_timing_stop(cwt_plan *P, float *ms_host, int32_t max, in
 extern "C" int cwt_plan_destroy(cwt_plan *P, void *stream)
 {
     if (!P) return CWT_OK;
-    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    clear_error();
+    // Stream-ordered: the frees are enqueued on `stream` behind the work
+    // already there; nothing here waits for the device.
     release_split_precision(*P);
-    free_plan_device(*P);
+    free_plan_device(*P, (hipStream_t)stream);
     for (hipEvent_t ev : P->timing_ev) (void)hipEventDestroy(ev);
     delete P;
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize in cwt_plan_destroy");
     return CWT_OK;
 }

@@ -489,6 +489,18 @@ extern "C" int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *w
                                        it.maxv, it.mode, (int64_t)it.lds});
     }
     shape.insert(shape.end(), {(int64_t)Lo.total, n});
+    // The items' plans may have been created on other streams: s waits for
+    // any whose tables are still being written.
+    {
+        std::vector<const cwt_plan *> seen;
+        for (int i = 0; i < n; ++i) {
+            const cwt_plan *P = items[i].plan;
+            if (std::find(seen.begin(), seen.end(), P) != seen.end()) continue;
+            seen.push_back(P);
+            rc = wait_plan_ready(*P, s);
+            if (rc != CWT_OK) return rc;
+        }
+    }
     e = hipMemcpyAsync(dws + Lo.fwd_items, h + Lo.fwd_items, table_bytes - Lo.fwd_items,
                        hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "batch table upload");

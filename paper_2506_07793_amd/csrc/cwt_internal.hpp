@@ -11,6 +11,15 @@
 
 struct cwt_split_state;  // split-precision (MFMA) tables, when built
 
+namespace cwtrt {
+// Allocator of a library object's device memory (both null: HIP's pool).
+struct DevMem {
+    cwt_alloc_fn alloc = nullptr;
+    cwt_free_fn free = nullptr;
+    void *ctx = nullptr;
+};
+}  // namespace cwtrt
+
 struct cwt_plan {
     int64_t n = 0;
     double sfreq = 0;
@@ -38,6 +47,22 @@ struct cwt_plan {
     int *d_grp_freq = nullptr;
     int *d_grp_off = nullptr;
     cwt_split_state *split = nullptr;
+    // Device memory the plan owns: every block came from mem (on the creation
+    // stream) and goes back through it on the destroy stream.
+    struct Block {
+        void *p;
+        size_t n;
+    };
+    cwtrt::DevMem mem{};
+    std::vector<Block> blocks;
+    // Recorded on the creation stream once the tables are written; the stream
+    // server and the batch entry point wait for it on their own streams.
+    hipEvent_t ready = nullptr;
+    // With opts.max_channels > 0: the plan's own workspace for that many
+    // channels (used when an execute call passes no workspace).
+    int64_t max_channels = 0;
+    void *own_ws = nullptr;
+    size_t own_ws_bytes = 0;
     // Per-launch timing of the transform kernel (cwt_plan_timing_start/stop):
     // event pairs bound to the next `timing_cap` transform dispatches.
     std::vector<hipEvent_t> timing_ev;  // 2 per slot: start, stop
@@ -62,7 +87,18 @@ int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
                       const cwt_plan_opts *opts);
 int check_device(int *dev_out);
 int upload_plan(cwt_plan &P, hipStream_t s);
-void free_plan_device(cwt_plan &P);
+// Frees the plan's device memory in stream order on s.
+void free_plan_device(cwt_plan &P, hipStream_t s);
+// Allocates the plan's own workspace (max_channels) and records P.ready on s.
+int finish_plan(cwt_plan &P, hipStream_t s);
+// Device memory (cwt_mem.cpp).
+int check_dev_mem(const DevMem &m);
+int dev_alloc(const DevMem &m, void **p, size_t bytes, hipStream_t s, const char *what);
+void dev_free(const DevMem &m, void *p, size_t bytes, hipStream_t s);
+int plan_alloc(cwt_plan &P, void **p, size_t bytes, hipStream_t s, const char *what);
+void plan_free_all(cwt_plan &P, hipStream_t s);
+// Make stream s wait until the plan's tables are written (no-op when they are).
+int wait_plan_ready(const cwt_plan &P, hipStream_t s);
 size_t workspace_bytes(const cwt_plan &P, int64_t C);
 int enqueue_forward(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride, void *ws,
                     hipStream_t s);

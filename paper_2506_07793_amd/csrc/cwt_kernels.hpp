@@ -87,19 +87,23 @@ hipError_t launch_item_main(const MainParams *items, int item, int blocks, int t
 // ----------------------------------------------------------- streaming --
 // One completed hop of one session.
 struct StreamJob {
-    float *ring;   // session ring [C][W]
+    float *ring;   // session ring [C][R]
     int pos;       // ring position of this hop's first sample
     int slab_off;  // offset of this hop's [C][hop] samples in the slab
     int emit_row;  // row block in the window batch (>= 0 when output is due)
     int pad_;
 };
 
+// Rings hold R >= W samples per channel: the hops of one session in one
+// launch are all appended before any window is gathered, so a window must
+// survive the appends of the session's later hops in that launch
+// (R = W + (K - 1) hop for K windows of a session per launch).
 struct StreamParams {
     const StreamJob *jobs;
     int n_jobs;
     const float *slab;  // [n_jobs][C][hop] new samples
     float *xb;          // [n_emit][C][W] unrolled windows (oldest sample first)
-    int C, W, hop;
+    int C, W, hop, R;
 };
 
 // Band power of the trailing hop of each window, by a direct partial
@@ -118,6 +122,8 @@ struct StreamBPParams {
     float *out;            // [rows][n_bands]
 };
 
+// Largest dynamic LDS of the stream band-power kernel (spectrum band bins x 8 B).
+constexpr int kStreamMaxLds = 159 * 1024;
 hipError_t launch_stream_append(const StreamParams &p, hipStream_t s);
 hipError_t launch_stream_gather(const StreamParams &p, hipStream_t s);
 hipError_t launch_stream_bandpower(const StreamBPParams &p, int max_bins, hipStream_t s);

@@ -1,9 +1,10 @@
 // HIP kernels of the streaming form: ring append, window gather and the
 // trailing-hop band power of each window.
 //
-// A session keeps the last W samples of each channel in a device ring.  Each
-// completed hop appends its samples; once W samples have arrived, the window
-// (oldest sample first) is transformed: the forward FFT of the window uses
+// A session keeps the last R >= W samples of each channel in a device ring.
+// Each completed hop appends its samples; once W samples have arrived, the
+// window of the W samples ending with the hop (oldest first) is transformed:
+// the forward FFT of the window uses
 // the plain path's kernel, and this file's k_stream_freqpower evaluates the
 // inverse transform only at the hop's trailing samples t = W - hop .. W - 1,
 //   W_f[t] = sum over stored bins b of X~[b] H_f[b] exp(2 pi i b t / L),
@@ -19,10 +20,10 @@ __global__ void k_stream_append(StreamParams p)
     const StreamJob jb = p.jobs[blockIdx.x];
     const int c = blockIdx.y;
     const float *src = p.slab + jb.slab_off + (int64_t)c * p.hop;
-    float *ring = jb.ring + (int64_t)c * p.W;
+    float *ring = jb.ring + (int64_t)c * p.R;
     for (int k = threadIdx.x; k < p.hop; k += blockDim.x) {
         int q = jb.pos + k;
-        if (q >= p.W) q -= p.W;
+        if (q >= p.R) q -= p.R;
         ring[q] = src[k];
     }
 }
@@ -32,14 +33,15 @@ __global__ void k_stream_gather(StreamParams p)
     const StreamJob jb = p.jobs[blockIdx.x];
     if (jb.emit_row < 0) return;
     const int c = blockIdx.y;
-    const float *ring = jb.ring + (int64_t)c * p.W;
+    const float *ring = jb.ring + (int64_t)c * p.R;
     float *dst = p.xb + ((int64_t)jb.emit_row * p.C + c) * p.W;
-    // oldest sample sits just after the newly appended hop
-    int start = jb.pos + p.hop;
-    if (start >= p.W) start -= p.W;
+    // the window ends with this job's hop: its oldest sample is W - hop
+    // slots before the hop's first one (pos, hop <= W <= R)
+    int start = jb.pos + p.hop - p.W;
+    if (start < 0) start += p.R;
     for (int k = threadIdx.x; k < p.W; k += blockDim.x) {
         int q = start + k;
-        if (q >= p.W) q -= p.W;
+        if (q >= p.R) q -= p.R;
         dst[k] = ring[q];
     }
 }
@@ -130,8 +132,15 @@ hipError_t launch_stream_bandpower(const StreamBPParams &p, int max_bins, hipStr
     if (p.rows == 0) return hipSuccess;
     if (p.n_grouped > 0) {
         const size_t lds = (size_t)(max_bins > 0 ? max_bins : 1) * sizeof(cf);
-        (void)hipFuncSetAttribute((const void *)k_stream_freqpower,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        // once per process, for the largest dynamic LDS any plan may ask for
+        // (stream sessions accept spectrum bands up to this size)
+        static const bool attr_set = [] {
+            (void)hipFuncSetAttribute((const void *)k_stream_freqpower,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)kStreamMaxLds);
+            return true;
+        }();
+        (void)attr_set;
         // one wave covers hops up to 64 samples; longer hops use two
         const int threads = p.hop <= 64 ? 64 : 128;
         hipLaunchKernelGGL(k_stream_freqpower, dim3(p.rows, p.n_grouped), dim3(threads), lds, s, p);

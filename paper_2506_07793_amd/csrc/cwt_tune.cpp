@@ -127,17 +127,20 @@ extern "C" int cwt_plan_autotune(cwt_plan *P, int64_t C, void *stream, cwt_tune_
     const size_t ws_b = workspace_bytes(*P, Ct);
     void *x = nullptr, *out = nullptr, *ws = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    // temporaries from the plan's allocator, freed in stream order on s
     auto cleanup = [&]() {
-        if (x) (void)hipFree(x);
-        if (out) (void)hipFree(out);
-        if (ws) (void)hipFree(ws);
+        dev_free(P->mem, x, x_b, s);
+        dev_free(P->mem, out, out_b, s);
+        dev_free(P->mem, ws, ws_b, s);
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
     };
-    if (hipMalloc(&x, x_b) != hipSuccess || hipMalloc(&out, out_b) != hipSuccess ||
-        hipMalloc(&ws, ws_b) != hipSuccess) {
+    int arc = dev_alloc(P->mem, &x, x_b, s, "autotune input");
+    if (arc == CWT_OK) arc = dev_alloc(P->mem, &out, out_b, s, "autotune output");
+    if (arc == CWT_OK) arc = dev_alloc(P->mem, &ws, ws_b, s, "autotune workspace");
+    if (arc != CWT_OK) {
         cleanup();
-        return fail(CWT_E_NOMEM, "autotune buffers");
+        return arc;
     }
     hipError_t e = hipMemsetAsync(x, 0, x_b, s);
     if (e == hipSuccess) e = hipEventCreate(&e0);

@@ -48,14 +48,20 @@ void cyclic_band(const std::vector<double> &mag, double thr, int &lo, int &K)
     K = L - best_gap;
 }
 
+// Device copy of count values of src (or uninitialised when src is NULL):
+// a plan-owned block when `owned`, else a temporary the caller frees.
 template <class T>
-int upload(T **dst, const T *src, size_t count, hipStream_t s, const char *what)
+int upload(cwt_plan &P, bool owned, T **dst, const T *src, size_t count, hipStream_t s,
+           const char *what)
 {
     *dst = nullptr;
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), std::max<size_t>(count, 1) * sizeof(T));
-    if (e != hipSuccess) return hip_fail(e, what);
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    void *p = nullptr;
+    int rc = owned ? plan_alloc(P, &p, bytes, s, what) : dev_alloc(P.mem, &p, bytes, s, what);
+    if (rc != CWT_OK) return rc;
+    *dst = static_cast<T *>(p);
     if (src && count) {
-        e = hipMemcpyAsync(*dst, src, count * sizeof(T), hipMemcpyHostToDevice, s);
+        hipError_t e = hipMemcpyAsync(*dst, src, count * sizeof(T), hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(e, what);
     }
     return CWT_OK;
@@ -64,13 +70,14 @@ int upload(T **dst, const T *src, size_t count, hipStream_t s, const char *what)
 int build_user_plan(cwt_plan &P, const float *wavelets, int64_t w_len, hipStream_t s)
 {
     const int F = P.F, L = P.L, wl = (int)w_len, c = wl / 2;
-    // device spectra, dense [F][L]
+    // device spectra, dense [F][L] (temporaries, freed in stream order below)
     float2 *d_w = nullptr, *d_Hd = nullptr;
     double2 *d_roots = nullptr;
-    int rc = upload(&d_w, reinterpret_cast<const float2 *>(wavelets), (size_t)F * wl, s,
-                    "wavelet upload");
-    if (rc == CWT_OK) rc = upload<double2>(&d_roots, nullptr, (size_t)L, s, "root table");
-    if (rc == CWT_OK) rc = upload<float2>(&d_Hd, nullptr, (size_t)F * L, s, "dense spectra");
+    int rc = upload(P, false, &d_w, reinterpret_cast<const float2 *>(wavelets), (size_t)F * wl,
+                    s, "wavelet upload");
+    if (rc == CWT_OK) rc = upload<double2>(P, false, &d_roots, nullptr, (size_t)L, s, "root table");
+    if (rc == CWT_OK)
+        rc = upload<float2>(P, false, &d_Hd, nullptr, (size_t)F * L, s, "dense spectra");
     std::vector<float2> Hd((size_t)F * L);
     if (rc == CWT_OK) {
         hipError_t e = launch_user_spectra(d_w, F, wl, c, L, d_roots, d_Hd, s);
@@ -80,8 +87,9 @@ int build_user_plan(cwt_plan &P, const float *wavelets, int64_t w_len, hipStream
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) rc = hip_fail(e, "sampled-wavelet spectra");
     }
-    for (void *p : {(void *)d_w, (void *)d_roots, (void *)d_Hd})
-        if (p) (void)hipFree(p);
+    dev_free(P.mem, d_w, std::max<size_t>((size_t)F * wl, 1) * sizeof(float2), s);
+    dev_free(P.mem, d_roots, std::max<size_t>((size_t)L, 1) * sizeof(double2), s);
+    dev_free(P.mem, d_Hd, std::max<size_t>((size_t)F * L, 1) * sizeof(float2), s);
     if (rc != CWT_OK) return rc;
 
     // bands and packing
@@ -109,14 +117,16 @@ int build_user_plan(cwt_plan &P, const float *wavelets, int64_t w_len, hipStream
     P.max_bins = maxK;
 
     // device tables: bands, packed complex spectra, twiddles, band groups
-    rc = upload(&P.d_freqs, P.freqs.data(), P.freqs.size(), s, "freqs");
-    if (rc == CWT_OK) rc = upload(&P.d_band, P.bands.data(), P.bands.size(), s, "bands");
-    if (rc == CWT_OK) rc = upload(&P.d_Hc, packed.data(), packed.size(), s, "complex spectra");
-    if (rc == CWT_OK) rc = upload<float2>(&P.d_tw, nullptr, (size_t)L, s, "twiddles");
+    rc = upload(P, true, &P.d_freqs, P.freqs.data(), P.freqs.size(), s, "freqs");
+    if (rc == CWT_OK) rc = upload(P, true, &P.d_band, P.bands.data(), P.bands.size(), s, "bands");
+    if (rc == CWT_OK)
+        rc = upload(P, true, &P.d_Hc, packed.data(), packed.size(), s, "complex spectra");
+    if (rc == CWT_OK) rc = upload<float2>(P, true, &P.d_tw, nullptr, (size_t)L, s, "twiddles");
     if (rc == CWT_OK && P.n_bands > 0) {
-        rc = upload(&P.d_grp_freq, P.grp_freq.data(), P.grp_freq.size(), s, "groups");
+        rc = upload(P, true, &P.d_grp_freq, P.grp_freq.data(), P.grp_freq.size(), s, "groups");
         if (rc == CWT_OK)
-            rc = upload(&P.d_grp_off, P.grp_off.data(), P.grp_off.size(), s, "group offs");
+            rc = upload(P, true, &P.d_grp_off, P.grp_off.data(), P.grp_off.size(), s,
+                        "group offs");
     }
     if (rc != CWT_OK) return rc;
     GenParams g{};  // twiddles only (no closed-form spectra)
@@ -176,8 +186,9 @@ extern "C" int cwt_plan_create_from_wavelets(cwt_plan **out, int64_t n, double s
     if (linear) P->opts.pad = CWT_PAD_LINEAR;
     if (rc == CWT_OK) rc = check_device(&P->device);
     if (rc == CWT_OK) rc = build_user_plan(*P, wavelets, w_len, (hipStream_t)stream);
+    if (rc == CWT_OK) rc = finish_plan(*P, (hipStream_t)stream);
     if (rc != CWT_OK) {
-        free_plan_device(*P);
+        free_plan_device(*P, (hipStream_t)stream);
         delete P;
         return rc;
     }

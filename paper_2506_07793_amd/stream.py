@@ -12,17 +12,32 @@ def now_ns():
 
 
 class Server:
-    """Batching stream server with an HBM budget (device memory of rings + workspaces)."""
+    """Batching stream server with an HBM budget (device memory of rings + workspaces).
 
-    def __init__(self, hbm_budget_bytes, max_batch=256, deadline_us=500, max_pending=64):
+    stream: the torch stream every device operation of the server goes on (a
+    new default-priority torch stream when None).  memory: "torch" (rings and
+    batch buffers from torch's caching allocator, the default), a
+    TorchDeviceMemory, or None (HIP's stream-ordered pool)."""
+
+    def __init__(self, hbm_budget_bytes, max_batch=256, deadline_us=500, max_pending=64,
+                 max_session_windows=4, stream=None, memory="torch"):
+        import torch
+
+        from . import TorchDeviceMemory
         lib = _lib.load()
         self._lib = lib
         o = _lib.ServerOpts()
         lib.cwt_server_opts_init(ctypes.byref(o))
         o.max_batch, o.deadline_us, o.max_pending = int(max_batch), int(deadline_us), int(max_pending)
+        o.max_session_windows = int(max_session_windows)
+        self.stream = torch.cuda.Stream() if stream is None else stream
+        self.memory = TorchDeviceMemory() if memory == "torch" else memory
+        if self.memory is not None:
+            self.memory.fill(o)
         h = ctypes.c_void_p()
         self._ptr = None
-        _lib.check(lib.cwt_server_create(ctypes.byref(h), int(hbm_budget_bytes), ctypes.byref(o)))
+        _lib.check(lib.cwt_server_create(ctypes.byref(h), int(hbm_budget_bytes), ctypes.byref(o),
+                                         ctypes.c_void_p(self.stream.cuda_stream)))
         self._ptr = h
         self.sessions = []
 

@@ -212,14 +212,24 @@ def test_stream_validation_without_gpu():
     lib = _lib.load()
     INV = _lib.CWT_E_INVALID
     h = ctypes.c_void_p()
-    assert lib.cwt_server_create(None, 1 << 20, None) == INV
+    assert lib.cwt_server_create(None, 1 << 20, None, None) == INV
     o = _lib.ServerOpts()
     lib.cwt_server_opts_init(ctypes.byref(o))
-    assert (o.max_batch, o.deadline_us, o.max_pending) == (256, 500, 64)
+    assert (o.max_batch, o.deadline_us, o.max_pending, o.max_session_windows) == (256, 500, 64, 4)
+    assert not o.alloc and not o.free
     o.max_batch = 0
-    assert lib.cwt_server_create(ctypes.byref(h), 1 << 20, ctypes.byref(o)) == INV
+    assert lib.cwt_server_create(ctypes.byref(h), 1 << 20, ctypes.byref(o), None) == INV
     lib.cwt_server_opts_init(ctypes.byref(o))
-    assert lib.cwt_server_create(ctypes.byref(h), 0, ctypes.byref(o)) == INV
+    assert lib.cwt_server_create(ctypes.byref(h), 0, ctypes.byref(o), None) == INV
+    lib.cwt_server_opts_init(ctypes.byref(o))
+    o.max_session_windows = 65
+    assert lib.cwt_server_create(ctypes.byref(h), 1 << 20, ctypes.byref(o), None) == INV
+    # an allocator needs both callbacks
+    lib.cwt_server_opts_init(ctypes.byref(o))
+    alloc_only = _lib.ALLOC_FN(lambda n, s, c: None)
+    o.alloc = alloc_only
+    assert lib.cwt_server_create(ctypes.byref(h), 1 << 20, ctypes.byref(o), None) == INV
+    assert b"together" in lib.cwt_last_error()
     assert not h.value
     assert lib.cwt_stream_open(None, None, 1, 1, ctypes.byref(h)) == INV
     assert lib.cwt_stream_push(None, None, 10, 0) == INV
@@ -333,3 +343,33 @@ def test_noalloc_source_makes_no_allocating_call():
     # and the symbol lookup
     bare = re.sub(r'"(?:[^"\\\n]|\\.)*"', '""', code)
     assert len(re.findall(r"\bscratch\b", bare)) == 2
+
+
+def test_plan_memory_options_validated_without_gpu():
+    """max_channels and the allocator callbacks are checked before any device
+    call: a negative max_channels or only one of alloc / free is CWT_E_INVALID,
+    and the descriptor reports max_channels."""
+    lib = _lib.load()
+    fp = (ctypes.c_double * 1)(10.0)
+    d = _lib.PlanDesc()
+    o = _lib.PlanOpts()
+    lib.cwt_plan_opts_init(ctypes.byref(o))
+    assert o.max_channels == 0 and not o.alloc and not o.free
+    o.max_channels = -1
+    assert lib.cwt_plan_describe(ctypes.byref(d), 100, 1000.0, fp, 1, None, 7.0,
+                                 ctypes.byref(o)) == _lib.CWT_E_INVALID
+    lib.cwt_plan_opts_init(ctypes.byref(o))
+    free_only = _lib.FREE_FN(lambda p, n, s, c: None)
+    o.free = free_only
+    assert lib.cwt_plan_describe(ctypes.byref(d), 100, 1000.0, fp, 1, None, 7.0,
+                                 ctypes.byref(o)) == _lib.CWT_E_INVALID
+    assert b"together" in lib.cwt_last_error()
+    h = ctypes.c_void_p()
+    assert lib.cwt_plan_create(ctypes.byref(h), 100, 1000.0, fp, 1, None, 7.0, ctypes.byref(o),
+                               None) == _lib.CWT_E_INVALID
+    assert not h.value
+    lib.cwt_plan_opts_init(ctypes.byref(o))
+    o.max_channels = 32
+    assert lib.cwt_plan_describe(ctypes.byref(d), 100, 1000.0, fp, 1, None, 7.0,
+                                 ctypes.byref(o)) == _lib.CWT_OK
+    assert d.max_channels == 32 and d.device_bytes == 0

@@ -139,7 +139,10 @@ def test_budget_backpressure_and_close():
     st = srv.stats()
     assert st["hbm_bytes_used"] <= st["hbm_budget_bytes"]
     s = opened[0]
-    # a push that would complete more than max_pending hops is refused whole
+    # the history before the first full window fills the ring and is not
+    # held against max_pending
+    assert s.push(np.zeros((C, W - hop), np.float32))
+    # a push that would complete more than max_pending window hops is refused whole
     assert not s.push(np.zeros((C, 4 * hop), np.float32))
     assert srv.stats()["rejected"] == 1
     assert s.push(np.zeros((C, 2 * hop), np.float32))
@@ -201,4 +204,68 @@ def test_serving_full_size(n_s, C, sfreq, W, hop):
     st = srv.stats()
     assert st["results"] == len(expect) * n_s and st["hops"] == n_s * (T // hop)
     srv.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("K", [1, 4, 9])
+def test_several_windows_of_a_session_per_launch(K):
+    """A session's whole recording pushed at once: the history before the
+    first full window and many window hops share launches (at most K windows
+    of the session per launch, rings of W + (K - 1) hop samples).  Every
+    window hop yields its result in order, matching the oracle, and the
+    results do not depend on K beyond rounding (the forward FFT packs two
+    window rows per complex transform, and with an odd channel count a row's
+    partner depends on how the hops were batched)."""
+    W, hop, sfreq, C = 1000, 50, 1000.0, 3
+    plan, freqs, cyc = _plan(W, sfreq, 24, 100.0)
+    x = synth.eeg(C, 2200, sfreq, seed=17)
+    out = {}
+    for k in (1, K):
+        srv = Server(1 << 30, max_batch=64, deadline_us=300, max_pending=64,
+                     max_session_windows=k)
+        s = srv.open(plan, C, hop)
+        assert s.push(x)
+        srv.flush()
+        res = []
+        while True:
+            r = s.poll()
+            if r is None:
+                break
+            res.append((r[0], r[1]))
+        st = srv.stats()
+        srv.close()
+        n_win = x.shape[1] // hop - (W // hop - 1)
+        assert [h for _, h in res] == list(range(W // hop - 1, x.shape[1] // hop))
+        assert st["results"] == n_win and st["hops"] == x.shape[1] // hop
+        # windows per launch bounded by k (plus one launch holding the history)
+        assert st["batches"] >= -(-n_win // k)
+        out[k] = res
+    _check(out[K], x, W, hop, sfreq, freqs, cyc, "K=%d" % K, max_checks=8)
+    for (a, ha), (b, hb) in zip(out[1], out[K]):
+        assert ha == hb
+        assert np.max(np.abs(a - b) / np.max(np.abs(b), axis=0, keepdims=True)) <= 2e-6
+    plan.close()
+
+
+def test_server_on_caller_stream():
+    """The server enqueues everything on the stream it is given; results
+    match the oracle and the caller's stream is left usable."""
+    W, hop, sfreq, C = 500, 25, 250.0, 2
+    plan, freqs, cyc = _plan(W, sfreq, 12, 100.0)
+    st = torch.cuda.Stream()
+    srv = Server(1 << 30, max_batch=8, deadline_us=200, stream=st)
+    assert srv.stream is st
+    s = srv.open(plan, C, hop)
+    x = synth.eeg(C, 700, sfreq, seed=23)
+    assert s.push(x)
+    srv.flush()
+    res = []
+    while True:
+        r = s.poll()
+        if r is None:
+            break
+        res.append((r[0], r[1]))
+    _check(res, x, W, hop, sfreq, freqs, cyc, "caller stream", max_checks=3)
+    srv.close()
+    st.synchronize()
     plan.close()
