@@ -138,7 +138,8 @@ def parse():
                     help="streaming server's batching deadline in microseconds (the longest "
                          "a completed hop waits for others to share its launch)")
     ap.add_argument("--stream-seconds", type=float, default=6.0,
-                    help="real-time length of each streaming run (0 skips the streaming runs)")
+                    help="real-time length of each streaming run (0 skips the streaming runs; "
+                         "60 gives the 60 s serving runs of the serving workload)")
     ap.add_argument("--length-sweep", type=int, default=1,
                     help="1: run the N = 100..2500 length sweep (0 skips it)")
     ap.add_argument("--preroll-ms", type=float, default=300.0,
@@ -222,11 +223,32 @@ def bench_batch(steps, n_rec=256):
     e1.record(stream)
     torch.cuda.synchronize()
     ms_loop = e0.elapsed_time(e1) / steps
+    # The persistent form (one persistent forward and one transform kernel
+    # per workgroup-size class, tasks claimed through atomic counters) on the
+    # same autotuned plans, for comparison with the default form.
+    old_k = os.environ.get("CWT_BATCH_KERNELS")
+    os.environ["CWT_BATCH_KERNELS"] = "persistent"
+    try:
+        batch.execute(ws)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            batch.execute(ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_pers = e0.elapsed_time(e1) / steps
+    finally:
+        if old_k is None:
+            os.environ.pop("CWT_BATCH_KERNELS", None)
+        else:
+            os.environ["CWT_BATCH_KERNELS"] = old_k
     res = {"workload": "%d seeded heterogeneous recordings, power out" % len(recs),
            "autotune_s": t_tune, "distinct_lengths": len(tuned),
            "points": pts, "out_GB": out_bytes / 1e9,
            "batch_graph_ms": ms_batch, "batch_pts_per_s": pts / (ms_batch * 1e-3),
            "per_recording_ms": ms_loop, "per_recording_pts_per_s": pts / (ms_loop * 1e-3),
+           "persistent_form_ms": ms_pers,
+           "persistent_form_over_graph": ms_pers / ms_batch,
            "batch_hbm_frac": (out_bytes + in_bytes) / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS}
     del items, batch, ws, wss
     for p in plans:
@@ -730,6 +752,18 @@ def main():
     del ring, fills, W32
     torch.cuda.empty_cache()
 
+    # Outputs of every precision and output mode on the first PREC_C channels,
+    # compared with the FP64 oracle in the CPU leg below.
+    PREC_C = 2
+    prec_out = {}
+    for prec in ("fp32", "split_f16", "split_bf16"):
+        for mode in ("complex64", "power", "bandpower"):
+            pp = cwt.Plan(N, cfg["sfreq"], cfg["freqs"], n_cycles=cfg["n_cycles"], out=mode,
+                          precision=prec)
+            prec_out[(prec, mode)] = pp.execute(x[:PREC_C]).cpu().numpy()
+            pp.close()
+    torch.cuda.synchronize()
+
     if args.out == "complex64":
         W_ref = plan.execute(x)
         result["library_baseline"] = bench_torch_fft(plan, x, C, N, F, stream, min(K, 50), W_ref)
@@ -766,6 +800,26 @@ def main():
             dt = time.perf_counter() - t0
             if dt >= args.cpu_seconds or passes >= 8:
                 break
+        # Each precision's error against the FP64 oracle, per output kind,
+        # on PREC_C channels x all frequencies x all samples (relative to the
+        # largest reference value of that output).
+        ref = oracle.cwt(xs[:PREC_C], cfg["sfreq"], cfg["freqs"], cfg["n_cycles"])
+        P_ref = oracle.power(ref)
+        BP_ref = oracle.band_power(P_ref, oracle.band_groups(cfg["freqs"]))
+        pvo = {"sample": "%d channels x %d freqs x %d samples of the workload above" % (
+            PREC_C, F, N)}
+        for prec in ("fp32", "split_f16", "split_bf16"):
+            Wg = prec_out[(prec, "complex64")].astype(np.complex128)
+            e = {}
+            dW = np.abs(Wg - ref) / np.abs(ref).max()
+            e["complex"] = {"max_rel_W": float(dW.max()), "mean_rel_W": float(dW.mean())}
+            for mode, R, key in (("power", P_ref, "power"), ("bandpower", BP_ref, "band_power")):
+                d = np.abs(prec_out[(prec, mode)].astype(np.float64) - R) / R.max()
+                e[key] = {"max_rel": float(d.max()), "mean_rel": float(d.mean())}
+            dP = np.abs(oracle.power(Wg) - P_ref) / P_ref.max()
+            e["power_of_complex"] = {"max_rel": float(dP.max()), "mean_rel": float(dP.mean())}
+            pvo[prec] = e
+        result["precision_vs_oracle"] = pvo
         result["cpu_baseline"] = {
             "value": passes * len(rows) * N / dt, "unit": "samples*freqs/s",
             "cores": oracle.num_threads(), "kind": "oracle",

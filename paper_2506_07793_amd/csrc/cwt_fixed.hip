@@ -286,14 +286,18 @@ __device__ __forceinline__ void fixed_main_row(const MainParams &p, int item)
 #pragma unroll
     for (int m = 0; m < kV; ++m) acc[m] = 0.f;
 
-    for (int q = qb; q < qe; ++q) {
+    // Complex and power rows are one transform: a trip count the compiler
+    // sees as 1, so nothing is hoisted out of a loop (and spilled) for them.
+    const int nq = (MODE == kOutBand) ? qe - qb : 1;
+    for (int qi = 0; qi < nq; ++qi) {
+        const int q = qb + qi;
         const int f = (MODE == kOutBand) ? p.grp_freq[q] : q;
         const BandDesc bd = p.band[f];
         const float *Hf = p.H + bd.off;
         const cf *Hcf = p.Hc ? reinterpret_cast<const cf *>(p.Hc) + bd.off : nullptr;
         const int K = bd.K;
         const int lo_u = bd.lo < 0 ? bd.lo + L : bd.lo;
-        if (q != qb) __syncthreads();  // previous transform finished with lds
+        if (qi > 0) __syncthreads();  // previous transform finished with lds
         cf v[kV];
         if (K <= kBandMax) {
             band_transform<L, TWM>(X, Hf, Hcf, lo_u, K, tw, lds, t, v);
