@@ -72,10 +72,12 @@ int64_t pad_length(int64_t n, int mode, int64_t explicit_len)
     }
 }
 
-// Composite radices the passes implement (small factors sharing one pass).
+// Composite radices the passes implement (small factors sharing one pass);
+// 20, 21 and 24 only in plans of 24 values per thread.
 static bool composite_radix(int r)
 {
-    return r == 6 || r == 9 || r == 10 || r == 12 || r == 14 || r == 15;
+    return r == 6 || r == 9 || r == 10 || r == 12 || r == 14 || r == 15 || r == 20 || r == 21 ||
+           r == 24;
 }
 
 // Fewest factors reachable from f by merging pairs into composite radices of
@@ -149,6 +151,8 @@ static bool try_radix_plan(int L, const int *order, int n_order, int maxv, bool 
     return false;
 }
 
+static void ranked_plans(int L, std::vector<RadixPlan> &out);
+
 void radix_candidates(int L, std::vector<RadixPlan> &out)
 {
     static const int o1[] = {16, 8, 4, 2, 7, 5, 3};
@@ -157,6 +161,15 @@ void radix_candidates(int L, std::vector<RadixPlan> &out)
     const int *orders[] = {o1, o2, o3};
     const int lens[] = {7, 6, 5};
     out.clear();
+    // the best-ranked schedules first (a few of them, at both workgroup sizes)
+    std::vector<RadixPlan> ranked;
+    ranked_plans(L, ranked);
+    for (size_t i = 0; i < ranked.size() && i < 4; ++i)
+        for (int mul = 1; mul <= 2; ++mul) {
+            RadixPlan c = ranked[i];
+            c.threads = ranked[i].threads * mul;
+            if (c.threads <= 1024) out.push_back(c);
+        }
     for (int maxv : {16, 24})
         for (bool merge : {true, false})
             for (int o = 0; o < 3; ++o) {
@@ -176,18 +189,94 @@ void radix_candidates(int L, std::vector<RadixPlan> &out)
             }
 }
 
+// Every radix the passes implement, largest first.
+static const int kRadices[] = {24, 21, 20, 16, 15, 14, 12, 10, 9, 8, 7, 6, 5, 4, 3, 2};
+
+// Workgroup size for a schedule at maxv values per thread: the smallest
+// multiple of 64 (at least L/16) for which every pass's butterflies fit, or
+// 0 when none up to 1024 does.
+static int schedule_threads(int L, const std::vector<int> &f, int maxv)
+{
+    int need = std::max(64, std::min(1024, ((L / 16 + 63) / 64) * 64));
+    for (int R : f) {
+        if (R > maxv) return 0;
+        const int mb = std::max(1, maxv / R);
+        const int t = (L / R + mb - 1) / mb;
+        need = std::max(need, ((t + 63) / 64) * 64);
+    }
+    return need <= 1024 ? need : 0;
+}
+
+// All schedules (radix multisets, largest radix first) whose product is L.
+static void enum_schedules(int rem, int maxr, std::vector<int> &cur,
+                           std::vector<std::vector<int>> &out)
+{
+    if (rem == 1) {
+        out.push_back(cur);
+        return;
+    }
+    if ((int)cur.size() >= kMaxPasses) return;
+    for (int r : kRadices)
+        if (r <= maxr && rem % r == 0) {
+            cur.push_back(r);
+            enum_schedules(rem / r, r, cur, out);
+            cur.pop_back();
+        }
+}
+
+// Feasible plans of length L ordered best first: fewest passes (each pass is
+// one LDS round trip and two barriers, and its twiddle products), then the
+// least lane work Σ T ceil((L/R)/T) R (idle lanes of partly filled
+// butterfly rounds count), then fewer values per thread.
+static void ranked_plans(int L, std::vector<RadixPlan> &out)
+{
+    out.clear();
+    std::vector<std::vector<int>> scheds;
+    std::vector<int> cur;
+    enum_schedules(L, 1 << 30, cur, scheds);
+    struct Cand {
+        RadixPlan rp;
+        int64_t work;
+    };
+    std::vector<Cand> c;
+    for (const auto &f : scheds)
+        for (int maxv : {16, 24}) {
+            const int T = schedule_threads(L, f, maxv);
+            if (!T) continue;
+            RadixPlan rp{};
+            rp.L = L;
+            rp.n_pass = (int)f.size();
+            for (int i = 0; i < rp.n_pass; ++i) rp.radix[i] = f[i];
+            rp.threads = T;
+            rp.maxv = maxv;
+            int64_t work = 0;
+            for (int R : f) work += (int64_t)T * ((L / R + T - 1) / T) * R;
+            c.push_back({rp, work});
+        }
+    std::stable_sort(c.begin(), c.end(), [](const Cand &a, const Cand &b) {
+        if (a.rp.n_pass != b.rp.n_pass) return a.rp.n_pass < b.rp.n_pass;
+        if (a.work != b.work) return a.work < b.work;
+        return a.rp.maxv < b.rp.maxv;
+    });
+    for (const Cand &x : c) out.push_back(x.rp);
+}
+
 bool make_radix_plan(int L, RadixPlan &rp)
 {
-    static const int o1[] = {16, 8, 4, 2, 7, 5, 3};
-    static const int o2[] = {8, 4, 2, 7, 5, 3};
-    static const int o3[] = {4, 2, 7, 5, 3};
-    for (int maxv : {16, 24})
-        for (bool merge : {true, false}) {
-            if (try_radix_plan(L, o1, 7, maxv, merge, rp)) return true;
-            if (try_radix_plan(L, o2, 6, maxv, merge, rp)) return true;
-            if (try_radix_plan(L, o3, 5, maxv, merge, rp)) return true;
-        }
-    return false;
+    if (L == 1) {  // a single identity pass
+        rp = RadixPlan{};
+        rp.L = 1;
+        rp.n_pass = 1;
+        rp.radix[0] = 1;
+        rp.threads = 64;
+        rp.maxv = 16;
+        return true;
+    }
+    std::vector<RadixPlan> ranked;
+    ranked_plans(L, ranked);
+    if (ranked.empty()) return false;
+    rp = ranked.front();
+    return true;
 }
 
 // Stored band of one frequency's spectrum: every signed bin whose value can

@@ -302,6 +302,15 @@ __device__ __forceinline__ void band_prologue_rt(int R0, bool sw, gptr<cf> X, gp
         else band_prologue<6, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
         break;
     case 15: band_prologue<15, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw); break;
+    case 20:
+        if (sw) band_prologue<20, true>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        else band_prologue<20, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        break;
+    case 24:
+        if (sw) band_prologue<24, true>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        else band_prologue<24, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw);
+        break;
+    case 21: band_prologue<21, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw); break;
     case 9: band_prologue<9, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw); break;
     case 7: band_prologue<7, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw); break;
     case 5: band_prologue<5, false>(X, Hf, Hcf, lo_u, K, L, Lh, Ns0, T, tid, tw); break;

@@ -84,7 +84,8 @@ void apply_tuning_cache(cwt_plan &P)
             q += used;
             // radices the passes implement
             if (ok && !(r == 1 || r == 2 || r == 3 || r == 4 || r == 5 || r == 6 || r == 7 ||
-                        r == 8 || r == 9 || r == 10 || r == 12 || r == 14 || r == 15 || r == 16))
+                        r == 8 || r == 9 || r == 10 || r == 12 || r == 14 || r == 15 || r == 16 ||
+                        ((r == 20 || r == 21 || r == 24) && r <= maxv)))
                 ok = 0;
             if (!ok) break;
             rp.radix[i] = r;

@@ -236,7 +236,7 @@ struct Dft<7, SIGN> : DftOdd<7, SIGN> {};
 
 // Composite radices R = R1 R2 (small factors merged into one pass, so that a
 // length does not spend an LDS round trip and two barriers on a radix-2 or
-// radix-3 pass): with r = R2 r1 + r2 and k = k1 + R1 k2,
+// radix-3 pass; 20, 21 and 24 only in plans of 24 values per thread): with r = R2 r1 + r2 and k = k1 + R1 k2,
 //   V[k] = sum_r2 W_R2^(r2 k2) [ W_R^(r2 k1) sum_r1 v[R2 r1 + r2] W_R1^(r1 k1) ],
 // W_M = exp(SIGN 2 pi i / M); wn[m] = W_R^m (table values, rounded once).
 template <int R>
@@ -249,6 +249,9 @@ template <> struct CompSplit<10> { static constexpr int r1 = 2, r2 = 5; };
 template <> struct CompSplit<12> { static constexpr int r1 = 4, r2 = 3; };
 template <> struct CompSplit<14> { static constexpr int r1 = 2, r2 = 7; };
 template <> struct CompSplit<15> { static constexpr int r1 = 3, r2 = 5; };
+template <> struct CompSplit<20> { static constexpr int r1 = 4, r2 = 5; };
+template <> struct CompSplit<21> { static constexpr int r1 = 3, r2 = 7; };
+template <> struct CompSplit<24> { static constexpr int r1 = 8, r2 = 3; };
 
 template <int R1, int R2, int SIGN>
 struct DftC {
@@ -391,6 +394,15 @@ __device__ __forceinline__ void stockham_pass_rt(int R, int L, int Ns, int T, in
     case 12: stockham_pass<12, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
     case 14: stockham_pass<14, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
     case 15: stockham_pass<15, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
+    case 20:
+        if constexpr (MAXV >= 20) stockham_pass<20, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store);
+        break;
+    case 21:
+        if constexpr (MAXV >= 21) stockham_pass<21, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store);
+        break;
+    case 24:
+        if constexpr (MAXV >= 24) stockham_pass<24, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store);
+        break;
     case 1: stockham_pass<1, SIGN, MAXV, SYNC_MID>(L, Ns, T, tid, tw, load, store); break;
     default: break;
     }

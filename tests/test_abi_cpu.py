@@ -69,23 +69,72 @@ def test_padded_length_and_radices(n, pad, expl, L):
     radix = [d.radix[i] for i in range(d.n_passes)]
     assert int(np.prod(radix)) == L
     # the radices the passes implement: primes and powers of two, and the
-    # composites 2x3, 3x3, 2x5, 4x3, 2x7, 3x5 that merge small factors
-    assert all(r in (1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 14, 15, 16) for r in radix)
+    # composites 2x3, 3x3, 2x5, 4x3, 2x7, 3x5 (and 4x5, 3x7, 8x3 in plans of
+    # 24 values per thread) that merge small factors
+    assert all(r in RADICES for r in radix)
     # no thread holds more values than the kernel's register budget
+    maxv = 16 if all(-(-(L // r) // d.threads) <= max(1, 16 // r) and r <= 16
+                     for r in radix) else 24
     for r in radix:
         nb = -(-(L // r) // d.threads)
-        assert nb <= max(1, 24 // r)
-        assert r <= 16
+        assert nb <= max(1, maxv // r)
+        assert r <= maxv
+
+
+RADICES = (1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 14, 15, 16, 20, 21, 24)
+
+
+def _fewest_feasible_passes(L):
+    """Brute force: the fewest passes of any schedule of implemented radices
+    whose product is L and whose butterflies fit one workgroup of at most
+    1024 threads holding at most 16 (or 24) values each (radices above 16
+    only at 24), with at least L/16 threads."""
+    best = None
+    for maxv in (16, 24):
+        rad = [r for r in RADICES if 1 < r <= maxv]
+        t_min = max(64, min(1024, -(-(L // 16) // 64) * 64))
+
+        def fits(r):
+            mb = max(1, maxv // r)
+            return -(-(-(-(L // r) // mb)) // 64) * 64 <= 1024 and t_min <= 1024
+
+        ok = [r for r in rad if fits(r)]
+        memo = {}
+
+        def rec(m):
+            if m == 1:
+                return 0
+            if m not in memo:
+                memo[m] = min([1 + rec(m // r) for r in ok if m % r == 0] or [99])
+            return memo[m]
+
+        n = rec(L)
+        best = n if best is None else min(best, n)
+    return best
+
+
+@pytest.mark.parametrize("L", [4116, 2187, 1680, 105, 98, 3072, 1000, 2000, 10000, 4096, 19440,
+                               20000, 16800, 18375, 12288, 7203])
+def test_planner_takes_fewest_passes(L):
+    """The schedule has the fewest passes any feasible schedule of the
+    implemented radices has (brute force here), largest radix first, and
+    fits the workgroup and register budget."""
+    d = cwt.describe(L, 1000.0, np.array([10.0, 20.0]), n_cycles=7.0, pad="explicit",
+                     explicit_len=L)
+    radix = [d.radix[i] for i in range(d.n_passes)]
+    assert int(np.prod(radix)) == L
+    assert radix == sorted(radix, reverse=True)
+    if d.kernel == 0:  # the runtime-radix kernel's schedule
+        assert d.n_passes == _fewest_feasible_passes(L), radix
 
 
 @pytest.mark.parametrize("L,radix", [
-    (4116, [12, 7, 7, 7]), (2187, [9, 9, 9, 3]), (1680, [16, 15, 7]), (105, [15, 7]),
-    (98, [14, 7]), (3072, [16, 16, 12]), (1000, [8, 5, 5, 5]), (10000, [16, 5, 5, 5, 5]),
-    (4096, [16, 16, 16]),
+    (1000, [10, 10, 10]), (2000, [20, 20, 5]), (4116, [21, 14, 14]), (2187, [9, 9, 9, 3]),
+    (105, [15, 7]), (98, [14, 7]), (4096, [16, 16, 16]),
 ])
 def test_composite_radices_save_passes(L, radix):
-    """Small leftover factors share a pass (fewest passes; largest radix
-    first), and lengths without such factors keep their schedule."""
+    """Small factors share a pass: 1000 = 10 x 10 x 10 (three passes instead
+    of 8 x 5 x 5 x 5), 2000 = 20 x 20 x 5, 4116 = 21 x 14 x 14."""
     d = cwt.describe(L, 1000.0, np.array([10.0, 20.0]), n_cycles=7.0, pad="explicit",
                      explicit_len=L)
     assert [d.radix[i] for i in range(d.n_passes)] == radix
