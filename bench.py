@@ -36,6 +36,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 
 
 PROFILES = {
@@ -120,7 +121,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--out", default="complex64", choices=["complex64", "power"])
+    ap.add_argument("--out", default="complex64", choices=["complex64", "power", "bandpower"],
+                    help="output of the timed transform (complex64: the headline; bandpower: the "
+                         "five EEG bands' mean power [C, 5, N])")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing (profiling runs)")
     ap.add_argument("--cpu-channels", type=int, default=64,
@@ -675,18 +678,35 @@ def main():
     pts = C * F * N
     value = pts / (ms_step * 1e-3)
     desc = plan.desc
+    # Algorithmic flops of one transform launch: 5 L log2 L per inverse
+    # transform (C x F of them) and 2 per stored spectrum bin per channel
+    # (the complex-by-real multiply)
+    import math
+    transform_flops = C * F * 5.0 * plan.L * math.log2(plan.L) + C * 2.0 * int(desc.spectrum_bins)
     elem = 8 if args.out == "complex64" else 4
+    out_elems = C * plan.out_rows * N  # F rows, or the bands' rows in band-power mode
     Lh = plan.L // 2 + 1
     # Algorithmic bytes of one launch of the transform kernel: every output
     # element written once, every channel half-spectrum and every stored
     # wavelet-spectrum bin read once; the pipelined launch also reads the
     # next batch's signal and writes its half spectra once.
-    transform_bytes = pts * elem + C * Lh * 8 + int(desc.spectrum_bins) * 4
+    transform_bytes = out_elems * elem + C * Lh * 8 + int(desc.spectrum_bins) * 4
     main_bytes = transform_bytes + (C * N * 4 + C * Lh * 8 if fused else 0)
     achieved = main_bytes / (ms_main * 1e-3) / 1e9
     # Whole step: the input signal and the spectra round trip as well.
-    step_bytes = pts * elem + C * Lh * 8 + int(desc.spectrum_bins) * 4 + C * N * 4 + C * Lh * 8
+    step_bytes = out_elems * elem + C * Lh * 8 + int(desc.spectrum_bins) * 4 + C * N * 4 + C * Lh * 8
 
+    if args.out == "bandpower":
+        # 5.2 MB of output per step: arithmetic, not HBM, bounds this mode
+        ach_tf = transform_flops / (ms_main * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": kernel_name(plan, fused), "achieved": ach_tf,
+                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach_tf / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "algorithmic_flops": transform_flops, "algorithmic_bytes": main_bytes,
+                "avg_ms": ms_main, "median_ms": float(np.median(kernel_ms)),
+                "kernel_avg_within_step": bool(ms_main <= ms_step)}
+    else:
+        roof = None
     result = {
         "metric": "CWT output samples x freqs per second (+ %HBM roofline; p99 stream window "
                   "latency)",
@@ -721,9 +741,11 @@ def main():
                      "kernel_avg_within_step": bool(ms_main <= ms_step),
                      # the same algorithmic bytes over the whole step (launch gaps
                      # included), the figure the step clock gives
-                     "step_frac": main_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                     "step_frac": main_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                    if roof is None else roof,
         "preroll": pre,
         "step_hbm_frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "store_bytes_per_launch": out_elems * elem,
         "output_ring": {"buffers": RING, "MB": RING * ob / 1e6},
         "one_output_buffer": one_buf,
         "ms_per_step_with_timing_events": ms_step_ev,

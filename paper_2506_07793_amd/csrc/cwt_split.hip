@@ -145,6 +145,17 @@ __global__ void __launch_bounds__(kT, 4) k_split_main(MainParams p)
         float2 *ocx = reinterpret_cast<float2 *>(p.out) + ((int64_t)c * p.n_rows + f) * N;
         float *opw = reinterpret_cast<float *>(p.out) + ((int64_t)c * p.n_rows + f) * N;
         if (qq != qb) __syncthreads();
+        // Over a band's frequencies this body repeats with the same lane, input
+        // row and twiddle table.  The compiler would hoist every address and
+        // index that depends only on those out of the loop, holding far more
+        // registers than the budget of four workgroups per CU leaves, and
+        // spill.  Here they are made opaque, so they are recomputed per
+        // frequency; the other modes run the body once and are unaffected.
+        const cf *Xq = X;
+        const cf *twq = tw;
+        int tq = tid;
+        if (MODE == kOutBand) asm volatile("" : "+s"(Xq), "+s"(twq), "+v"(tq));
+        const int wave = tq >> 6, n = (tq & 63) & 15, q = (tq & 63) >> 4;
 
         // A band of at most L/16 bins leaves one nonzero input in each
         // first-stage butterfly (the 16 inputs j + 256 r lie 256 bins apart):
@@ -155,19 +166,19 @@ __global__ void __launch_bounds__(kT, 4) k_split_main(MainParams p)
         if (band) {
 #pragma unroll 1
             for (int m = 0; m < kL / kT; ++m) {
-                const int d = tid + kT * m;  // first-stage output slot 16 j + k
+                const int d = tq + kT * m;  // first-stage output slot 16 j + k
                 const int j = d >> 4, k = d & 15;
                 const int o = (j - lo_u) & 255;  // band offset of the bin = j mod 256
                 cf val = mk(0.f, 0.f);
                 if (o < K) {
                     const int b = (lo_u + o) & (kL - 1);
                     const bool upper = b > kL / 2;
-                    cf xv = X[upper ? kL - b : b];
+                    cf xv = Xq[upper ? kL - b : b];
                     if (upper) xv.y = -xv.y;
                     // exp(2 pi i r0 k / 16) of input r0 = b div 256, then the
                     // second stage's twiddle of slot d (d div 256 = m)
                     const cf y = mul(scale(xv, Hf[o]), root16[((b >> 8) * k) & 15]);
-                    val = mul(y, tw[(16 * k * m) & (kL - 1)]);
+                    val = mul(y, twq[(16 * k * m) & (kL - 1)]);
                 }
                 lds[d] = val;
             }
@@ -192,7 +203,7 @@ __global__ void __launch_bounds__(kT, 4) k_split_main(MainParams p)
                         float val = 0.f;
                         if (o < K) {
                             const bool upper = idx > kL / 2;
-                            const cf xv = X[upper ? kL - idx : idx];
+                            const cf xv = Xq[upper ? kL - idx : idx];
                             const float part = (q >> 1) ? (upper ? -xv.y : xv.y) : xv.x;
                             val = part * Hf[o];
                         }
@@ -243,7 +254,7 @@ __global__ void __launch_bounds__(kT, 4) k_split_main(MainParams p)
                         // next stage's twiddle on its input element (d mod 256, d / 256)
                         const int Nn = Ns * 16;
                         const int jn = d & 255, rn = d >> 8;
-                        y = mul(y, tw[(jn & (Nn - 1)) * rn * (kL / (Nn * 16))]);
+                        y = mul(y, twq[(jn & (Nn - 1)) * rn * (kL / (Nn * 16))]);
                         lds[d] = y;
                     } else if (MODE == kOutBand) {
                         acc[g][i] += y.x * y.x + y.y * y.y;
