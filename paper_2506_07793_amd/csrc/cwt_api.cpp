@@ -553,6 +553,22 @@ static int dev_upload(cwt_plan &P, T **dst, const T *src, size_t count, hipStrea
     return CWT_OK;
 }
 
+// The band-power kernels take a band's frequencies one after another in one
+// workgroup, so the band with the most frequencies is the longest job; its
+// workgroups are launched first (longest-processing-time-first order), the
+// order appended here after the offsets.  Ties keep the band order.
+void set_group_table(cwt_plan &P)
+{
+    const int nb = (int)P.grp_off.size() - 1;
+    P.grp_table = P.grp_off;
+    std::vector<int> order(nb);
+    for (int b = 0; b < nb; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&P](int a, int b) {
+        return P.grp_off[a + 1] - P.grp_off[a] > P.grp_off[b + 1] - P.grp_off[b];
+    });
+    P.grp_table.insert(P.grp_table.end(), order.begin(), order.end());
+}
+
 void free_plan_device(cwt_plan &P, hipStream_t s)
 {
     plan_free_all(P, s);
@@ -582,7 +598,8 @@ int upload_plan(cwt_plan &P, hipStream_t s)
         if ((rc = dev_upload(P, &P.d_grp_freq, P.grp_freq.data(), P.grp_freq.size(), s,
                              "groups")))
             return rc;
-        if ((rc = dev_upload(P, &P.d_grp_off, P.grp_off.data(), P.grp_off.size(), s,
+        set_group_table(P);
+        if ((rc = dev_upload(P, &P.d_grp_off, P.grp_table.data(), P.grp_table.size(), s,
                              "group offs")))
             return rc;
     }

@@ -253,6 +253,15 @@ __device__ __forceinline__ void band_transform(const cf *__restrict__ X,
 
 // ------------------------------------------------------------ inverse --
 
+// Band-power workgroups run RowSub transforms side by side: sub-group g of
+// T threads owns LDS slab g and takes frequencies g, g + RowSub, ... of the
+// band, so a band of n frequencies is a chain of n / RowSub transform rounds
+// rather than n.  Complex and power rows are one transform per workgroup.
+template <int MODE, int L>
+struct RowSub {
+    static constexpr int value = (MODE != kOutBand) ? 1 : (L <= 4096 ? 4 : 2);
+};
+
 // One output row (channel, frequency or band) item of the transform.
 template <int MODE, int TWM, int... Rs>
 __device__ __forceinline__ void fixed_main_row(const MainParams &p, int item)
@@ -260,14 +269,21 @@ __device__ __forceinline__ void fixed_main_row(const MainParams &p, int item)
     using RL = RList<Rs...>;
     constexpr int L = RL::product;
     constexpr int T = L / kV;
+    constexpr int SUB = RowSub<MODE, L>::value;
     static_assert(RL::first == kV, "the first pass must be radix 16");
-    extern __shared__ cf lds[];
-    const int t = threadIdx.x;
+    extern __shared__ cf lds_all[];
     const int N = p.N;
-    const cf *tw = reinterpret_cast<const cf *>(p.tw);
 
-    const int c = item / p.n_rows;
-    const int row = item - c * p.n_rows;
+    int c, row;
+    if (MODE == kOutBand) {
+        // bands largest first, channel fastest
+        const int rank = item / p.C;
+        c = item - rank * p.C;
+        row = p.grp_off[p.n_rows + 1 + rank];
+    } else {
+        c = item / p.n_rows;
+        row = item - c * p.n_rows;
+    }
     int qb, qe;
     if (MODE == kOutBand) {
         qb = p.grp_off[row];
@@ -276,30 +292,53 @@ __device__ __forceinline__ void fixed_main_row(const MainParams &p, int item)
         qb = row;
         qe = row + 1;
     }
-    const cf *X = reinterpret_cast<const cf *>(p.Xh) + (int64_t)c * p.Lh;
-    float *orow_band = reinterpret_cast<float *>(p.out) + ((int64_t)c * p.n_rows + row) * N;
-    const float inv_n = 1.0f / (float)(qe - qb);
-    // Band power: thread t owns samples t + T m of every frequency's
-    // transform, so the sum over the band's frequencies stays in registers
-    // and the row is stored once.
+    const cf *X0 = reinterpret_cast<const cf *>(p.Xh) + (int64_t)c * p.Lh;
+    const cf *tw0 = reinterpret_cast<const cf *>(p.tw);
+    // Band power: thread t of a sub-group owns samples t + T m of each of its
+    // frequencies' transforms, so its share of the band sum stays in
+    // registers; the sub-groups' sums meet in LDS at the end.
     float acc[kV];
 #pragma unroll
     for (int m = 0; m < kV; ++m) acc[m] = 0.f;
 
     // Complex and power rows are one transform: a trip count the compiler
-    // sees as 1, so nothing is hoisted out of a loop (and spilled) for them.
+    // sees as 1.
     const int nq = (MODE == kOutBand) ? qe - qb : 1;
-    for (int qi = 0; qi < nq; ++qi) {
-        const int q = qb + qi;
+    const int rounds = (nq + SUB - 1) / SUB;
+    for (int r = 0; r < rounds; ++r) {
+        // Over a band's rounds the lane, input row and twiddle table stay the
+        // same; hoisted out of the loop, every address derived from them would
+        // be held in registers across it (and spilled).  Made opaque here they
+        // are recomputed per round.
+        int tid = threadIdx.x;
+        const cf *X = X0;
+        const cf *tw = tw0;
+        if (MODE == kOutBand) asm volatile("" : "+v"(tid), "+s"(X), "+s"(tw));
+        const int g = (SUB == 1) ? 0 : tid / T;
+        const int t = (SUB == 1) ? tid : tid - g * T;
+        cf *lds = lds_all + g * L;
+        const int qi = r * SUB + g;
+        const bool live = qi < nq;  // a short last round repeats the band's last frequency
+        const int q = qb + (live ? qi : nq - 1);
         const int f = (MODE == kOutBand) ? p.grp_freq[q] : q;
         const BandDesc bd = p.band[f];
         const float *Hf = p.H + bd.off;
         const cf *Hcf = p.Hc ? reinterpret_cast<const cf *>(p.Hc) + bd.off : nullptr;
         const int K = bd.K;
         const int lo_u = bd.lo < 0 ? bd.lo + L : bd.lo;
-        if (qi > 0) __syncthreads();  // previous transform finished with lds
+        // One path for the whole workgroup (the paths differ in their
+        // barriers): the band path only when every transform of the round fits.
+        bool narrow = K <= kBandMax;
+        if (SUB > 1) {
+#pragma unroll
+            for (int j = 0; j < SUB; ++j) {
+                const int qj = qb + min(r * SUB + j, nq - 1);
+                narrow = narrow && p.band[p.grp_freq[qj]].K <= kBandMax;
+            }
+        }
+        if (r > 0) __syncthreads();  // previous transforms finished with lds
         cf v[kV];
-        if (K <= kBandMax) {
+        if (narrow) {
             band_transform<L, TWM>(X, Hf, Hcf, lo_u, K, tw, lds, t, v);
         } else {
             // Band products y[k] = X~[b] H[k], b = lo + k (mod L), into lds[0, K).
@@ -329,8 +368,10 @@ __device__ __forceinline__ void fixed_main_row(const MainParams &p, int item)
         }
         // epilogue: v[m] is sample t + T m
         if (MODE == kOutBand) {
+            if (live) {
 #pragma unroll
-            for (int m = 0; m < kV; ++m) acc[m] += v[m].x * v[m].x + v[m].y * v[m].y;
+                for (int m = 0; m < kV; ++m) acc[m] += v[m].x * v[m].x + v[m].y * v[m].y;
+            }
             continue;
         }
         float2 *ocx = reinterpret_cast<float2 *>(p.out) + ((int64_t)c * p.n_rows + f) * N;
@@ -354,21 +395,46 @@ __device__ __forceinline__ void fixed_main_row(const MainParams &p, int item)
         }
     }
     if (MODE == kOutBand) {
+        float *orow = reinterpret_cast<float *>(p.out) + ((int64_t)c * p.n_rows + row) * N;
+        const float inv_n = 1.0f / (float)nq;
+        const int tid = threadIdx.x;
+        if (SUB == 1) {
 #pragma unroll
-        for (int m = 0; m < kV; ++m)
-            if (N == L || t + T * m < N) orow_band[t + T * m] = acc[m] * inv_n;
+            for (int m = 0; m < kV; ++m)
+                if (N == L || tid + T * m < N) orow[tid + T * m] = acc[m] * inv_n;
+        } else {
+            // sub-group sums through LDS (slab g holds L floats of sub-group
+            // g), added in sub-group order and stored once
+            float *ldsf = reinterpret_cast<float *>(lds_all);
+            const int g = tid / T, t = tid - g * T;
+            __syncthreads();  // every sub-group is done with its slab
+#pragma unroll
+            for (int m = 0; m < kV; ++m) ldsf[g * L + t + T * m] = acc[m];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < L / (SUB * T); ++i) {
+                const int o = tid + SUB * T * i;
+                float a = ldsf[o];
+#pragma unroll
+                for (int j = 1; j < SUB; ++j) a += ldsf[j * L + o];
+                if (N == L || o < N) orow[o] = a * inv_n;
+            }
+        }
     }
 }
 
-// Occupancy of the transform kernels: 5 waves per SIMD for L = 4096 (the LDS
-// of 5 workgroups fills the CU), no constraint otherwise.
+// Occupancy of the transform kernels: 5 waves per SIMD for complex and power
+// rows at L = 4096 (the LDS of 5 workgroups fills the CU), 4 for the
+// band-power workgroups of several sub-groups, no constraint otherwise.
 template <int MODE, int L>
 struct FixedWaves {
-    static constexpr int value = (MODE != kOutBand && L == 4096) ? 5 : 1;
+    static constexpr int value =
+        (MODE != kOutBand && L == 4096) ? 5 : (RowSub<MODE, L>::value > 1 ? 4 : 1);
 };
 
 template <int MODE, int TWM, int... Rs>
-__global__ void __launch_bounds__(RList<Rs...>::product / kV)
+__global__ void __launch_bounds__((RList<Rs...>::product / kV *
+                                   RowSub<MODE, RList<Rs...>::product>::value))
     __attribute__((amdgpu_waves_per_eu(FixedWaves<MODE, RList<Rs...>::product>::value)))
     k_fixed_main(MainParams p)
 {
@@ -380,36 +446,42 @@ __global__ void __launch_bounds__(RList<Rs...>::product / kV)
 // registers, then the separation X0 = (Z[b] + conj Z[-b]) / 2,
 // X1 = (Z[b] - conj Z[-b]) / (2i) through LDS.
 
-template <int... Rs>
-__device__ __forceinline__ void fixed_forward_pair(const FwdParams &p, int pair)
+// Thread t of a group of T threads with its own LDS slab transforms channel
+// pair `pair`.  With MAYBE_PAST_END, pairs past the last channel compute on
+// zeros and store nothing, so every group of a workgroup meets the same
+// barriers; without it every pair exists (one group per workgroup).
+template <bool MAYBE_PAST_END, int... Rs>
+__device__ __forceinline__ void fixed_forward_pair(const FwdParams &p, int pair, int t, cf *lds)
 {
     using RL = RList<Rs...>;
     constexpr int L = RL::product;
     constexpr int T = L / kV;
-    extern __shared__ cf lds[];
-    const int t = threadIdx.x;
     const int c0 = 2 * pair;
+    const bool has0 = !MAYBE_PAST_END || c0 < p.C;
     const bool has1 = (c0 + 1) < p.C;
-    const float *x0 = p.x + (int64_t)c0 * p.x_stride;
-    const float *x1 = p.x + (int64_t)(c0 + 1) * p.x_stride;
     const cf *tw = reinterpret_cast<const cf *>(p.tw);
     const int N = p.N;
     cf v[kV];
+    {
+        const float *x0 = p.x + (int64_t)(has0 ? c0 : 0) * p.x_stride;
+        const float *x1 = p.x + (int64_t)(has1 ? c0 + 1 : 0) * p.x_stride;
 #pragma unroll
-    for (int m = 0; m < kV; ++m) {
-        const int idx = t + T * m;
-        cf z = mk(0.f, 0.f);
-        if (idx < N) {
-            z.x = x0[idx];
-            if (has1) z.y = x1[idx];
+        for (int m = 0; m < kV; ++m) {
+            const int idx = t + T * m;
+            cf z = mk(0.f, 0.f);
+            if (has0 && idx < N) {
+                z.x = x0[idx];
+                if (has1) z.y = x1[idx];
+            }
+            v[m] = z;
         }
-        v[m] = z;
     }
     run_passes<-1, L, 1, kTwPowers>(v, t, tw, lds, RL{});
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < kV; ++m) lds[sw(t + T * m)] = v[m];
     __syncthreads();
+    if (!has0) return;  // no barrier follows
     float2 *X0 = p.Xh + (int64_t)c0 * p.Lh;
     float2 *X1 = X0 + p.Lh;
     for (int b = t; b < p.Lh; b += T) {
@@ -425,23 +497,32 @@ __device__ __forceinline__ void fixed_forward_pair(const FwdParams &p, int pair)
 template <int... Rs>
 __global__ void __launch_bounds__(RList<Rs...>::product / kV) k_fixed_forward(FwdParams p)
 {
-    fixed_forward_pair<Rs...>(p, blockIdx.x);
+    extern __shared__ cf lds[];
+    fixed_forward_pair<false, Rs...>(p, blockIdx.x, threadIdx.x, lds);
 }
 
 // Transform of one batch and forward FFT of the next in one launch: blocks
 // [0, n_fwd) take the forward role (channel pairs of the next batch, into the
-// other half of the workspace) and start first, the rest the transform rows,
-// so the short forward work runs beside the transform instead of between two
-// launches.
+// other half of the workspace; RowSub pairs per block, one per group of T
+// threads) and start first, the rest the transform rows, so the short
+// forward work runs beside the transform instead of between two launches.
 template <int MODE, int TWM, int... Rs>
-__global__ void __launch_bounds__(RList<Rs...>::product / kV)
+__global__ void __launch_bounds__((RList<Rs...>::product / kV *
+                                   RowSub<MODE, RList<Rs...>::product>::value))
     __attribute__((amdgpu_waves_per_eu(FixedWaves<MODE, RList<Rs...>::product>::value)))
     k_fixed_fused(MainParams p, FwdParams f, int n_fwd)
 {
-    if ((int)blockIdx.x < n_fwd)
-        fixed_forward_pair<Rs...>(f, blockIdx.x);
-    else
+    constexpr int L = RList<Rs...>::product;
+    constexpr int T = L / kV;
+    constexpr int SUB = RowSub<MODE, L>::value;
+    if ((int)blockIdx.x < n_fwd) {
+        extern __shared__ cf lds[];
+        const int g = (SUB == 1) ? 0 : (int)threadIdx.x / T;
+        fixed_forward_pair<(SUB > 1), Rs...>(f, (int)blockIdx.x * SUB + g,
+                                             (int)threadIdx.x - g * T, lds + g * L);
+    } else {
         fixed_main_row<MODE, TWM, Rs...>(p, blockIdx.x - n_fwd);
+    }
 }
 
 template <int... Rs>
@@ -475,7 +556,8 @@ template <int MODE, int TWM, int... Rs>
 static hipError_t launch_fixed_t(const MainParams &p, hipStream_t s, LaunchEvents ev)
 {
     constexpr int L = RList<Rs...>::product;
-    const size_t lds = (size_t)L * sizeof(cf);
+    constexpr int SUB = RowSub<MODE, L>::value;
+    const size_t lds = (size_t)SUB * L * sizeof(cf);
     // once per process (thread-safe static initialisation)
     static const bool attr_set = [lds] {
         (void)hipFuncSetAttribute((const void *)k_fixed_main<MODE, TWM, Rs...>,
@@ -483,8 +565,8 @@ static hipError_t launch_fixed_t(const MainParams &p, hipStream_t s, LaunchEvent
         return true;
     }();
     (void)attr_set;
-    hipExtLaunchKernelGGL((k_fixed_main<MODE, TWM, Rs...>), dim3(p.C * p.n_rows), dim3(L / kV),
-                          lds, s, ev.start, ev.stop, 0, p);
+    hipExtLaunchKernelGGL((k_fixed_main<MODE, TWM, Rs...>), dim3(p.C * p.n_rows),
+                          dim3(SUB * L / kV), lds, s, ev.start, ev.stop, 0, p);
     return hipGetLastError();
 }
 
@@ -510,7 +592,8 @@ static hipError_t launch_fused_t(const MainParams &p, const FwdParams &f, hipStr
                                  LaunchEvents ev)
 {
     constexpr int L = RList<Rs...>::product;
-    const size_t lds = (size_t)L * sizeof(cf);
+    constexpr int SUB = RowSub<MODE, L>::value;
+    const size_t lds = (size_t)SUB * L * sizeof(cf);
     // once per process (thread-safe static initialisation)
     static const bool attr_set = [lds] {
         (void)hipFuncSetAttribute((const void *)k_fixed_fused<MODE, TWM, Rs...>,
@@ -518,9 +601,9 @@ static hipError_t launch_fused_t(const MainParams &p, const FwdParams &f, hipStr
         return true;
     }();
     (void)attr_set;
-    const int n_fwd = (f.C + 1) / 2;
+    const int n_fwd = ((f.C + 1) / 2 + SUB - 1) / SUB;
     hipExtLaunchKernelGGL((k_fixed_fused<MODE, TWM, Rs...>), dim3(n_fwd + p.C * p.n_rows),
-                          dim3(L / kV), lds, s, ev.start, ev.stop, 0, p, f, n_fwd);
+                          dim3(SUB * L / kV), lds, s, ev.start, ev.stop, 0, p, f, n_fwd);
     return hipGetLastError();
 }
 

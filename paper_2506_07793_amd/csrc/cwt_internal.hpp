@@ -32,6 +32,9 @@ struct cwt_plan {
     std::vector<double> freqs, sigmas, band_edges;
     std::vector<cwtk::BandDesc> bands;
     std::vector<int> grp_freq, grp_off, band_of_freq;
+    // What d_grp_off holds: grp_off, then the band indices by frequency
+    // count, largest first (set by set_group_table)
+    std::vector<int> grp_table;
     int total_bins = 0;
     int max_bins = 0;
     bool use_fixed = false;  // register-resident kernel for this length
@@ -87,6 +90,8 @@ int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
                       const cwt_plan_opts *opts);
 int check_device(int *dev_out);
 int upload_plan(cwt_plan &P, hipStream_t s);
+// Fill P.grp_table from P.grp_off (band-power plans).
+void set_group_table(cwt_plan &P);
 // Frees the plan's device memory in stream order on s.
 void free_plan_device(cwt_plan &P, hipStream_t s);
 // Allocates the plan's own workspace (max_channels) and records P.ready on s.

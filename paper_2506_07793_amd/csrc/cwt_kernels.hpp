@@ -53,7 +53,8 @@ struct MainParams {
     int N, F, C;
     int n_rows;            // rows per channel in the output (F or n_bands)
     const int *grp_freq;   // band mode: frequency indices, band after band
-    const int *grp_off;    // band mode: [n_bands + 1] offsets into grp_freq
+    const int *grp_off;    // band mode: [n_bands + 1] offsets into grp_freq, then the
+                           // [n_bands] band indices by frequency count, largest first
     RadixPlan rp;
     int variant;           // register-resident kernel: 0 table twiddles, 1 power twiddles
 };

@@ -124,8 +124,9 @@ int build_user_plan(cwt_plan &P, const float *wavelets, int64_t w_len, hipStream
     if (rc == CWT_OK) rc = upload<float2>(P, true, &P.d_tw, nullptr, (size_t)L, s, "twiddles");
     if (rc == CWT_OK && P.n_bands > 0) {
         rc = upload(P, true, &P.d_grp_freq, P.grp_freq.data(), P.grp_freq.size(), s, "groups");
+        set_group_table(P);
         if (rc == CWT_OK)
-            rc = upload(P, true, &P.d_grp_off, P.grp_off.data(), P.grp_off.size(), s,
+            rc = upload(P, true, &P.d_grp_off, P.grp_table.data(), P.grp_table.size(), s,
                         "group offs");
     }
     if (rc != CWT_OK) return rc;
