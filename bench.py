@@ -40,9 +40,15 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector, published
 
 
 PROFILES = {
-    "fused": os.path.join(ROOT, "profiles", "k_fixed_fused_64ch_4096x100f_complex64.md"),
-    "main": os.path.join(ROOT, "profiles", "k_fixed_main_64ch_4096x100f_complex64.md"),
+    ("fused", "complex64"): os.path.join(ROOT, "profiles", "k_fixed_fused_64ch_4096x100f_complex64.md"),
+    ("main", "complex64"): os.path.join(ROOT, "profiles", "k_fixed_main_64ch_4096x100f_complex64.md"),
+    ("fused", "bandpower"): os.path.join(ROOT, "profiles", "k_fixed_fused_64ch_4096x100f_bandpower.md"),
 }
+
+
+def progress(msg):
+    """One line on stderr as each leg ends (stdout carries only the JSON line)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def committed_traffic(plan, out, kind):
@@ -51,8 +57,8 @@ def committed_traffic(plan, out, kind):
     the kernel sources no longer hash to the profiled ones or the workload
     differs from the profiled one."""
     import hashlib
-    path = PROFILES.get(kind)
-    if plan.desc.kernel != 1 or out != "complex64" or not path or not os.path.exists(path):
+    path = PROFILES.get((kind, out))
+    if plan.desc.kernel != 1 or not path or not os.path.exists(path):
         return None
     fields = {}
     for line in open(path):
@@ -701,7 +707,8 @@ def main():
         ach_tf = transform_flops / (ms_main * 1e-3) / 1e12
         roof = {"bound": "alu", "kernel": kernel_name(plan, fused), "achieved": ach_tf,
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach_tf / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "frac": ach_tf / FP32_VECTOR_PEAK_TFLOPS,
+                "traffic": committed_traffic(plan, args.out, "fused" if fused else "main"),
                 "algorithmic_flops": transform_flops, "algorithmic_bytes": main_bytes,
                 "avg_ms": ms_main, "median_ms": float(np.median(kernel_ms)),
                 "kernel_avg_within_step": bool(ms_main <= ms_step)}
@@ -813,23 +820,28 @@ def main():
         del W_ref
         torch.cuda.empty_cache()
 
+    progress("plain transform done: %.4f ms per step" % ms_step)
     if args.batch_steps > 0:
         result["batch"] = bench_batch(args.batch_steps)
+        progress("batch done")
 
     if args.length_sweep:
         result["length_sweep"] = bench_length_sweep()
+        progress("length sweep done")
 
     if args.stream_seconds > 0:
-        result["stream"] = [
-            bench_stream(512, 64, 1000.0, 2.0, 0.05, args.stream_seconds, 5, 512,
-                         args.stream_deadline_us),
-            bench_stream(64, 256, 2048.0, 2.0, 102 / 2048.0, args.stream_seconds, 6, 64,
-                         args.stream_deadline_us),
+        legs = [
+            ((512, 64, 1000.0, 2.0, 0.05), 5, 512, {}),
+            ((64, 256, 2048.0, 2.0, 102 / 2048.0), 6, 64, {}),
             # the first workload with linear-edge plans: no cyclic wrap of the
             # window's oldest samples reaches the trailing hop
-            bench_stream(512, 64, 1000.0, 2.0, 0.05, args.stream_seconds, 5, 512,
-                         args.stream_deadline_us, pad="linear"),
+            ((512, 64, 1000.0, 2.0, 0.05), 5, 512, {"pad": "linear"}),
         ]
+        result["stream"] = []
+        for (ns, sc, sf, win, hop), seed, mb, kw in legs:
+            result["stream"].append(bench_stream(ns, sc, sf, win, hop, args.stream_seconds, seed,
+                                                 mb, args.stream_deadline_us, **kw))
+            progress("serving leg %d sessions x %d ch %s done" % (ns, sc, kw.get("pad", "")))
         result["p99_stream_ms"] = result["stream"][0]["p99_ms"]
 
     if not args.no_cpu_baseline:
