@@ -395,44 +395,58 @@ def bench_stream(n_sessions, C, sfreq, win_s, hop_s, seconds, seed, max_batch, d
     ev = 0
     last_drain = 0.0
     pushed = 0
-    while True:
-        now = time.perf_counter() - t0
-        if now >= seconds:
-            break
-        while ev < len(events) and events[ev][0] <= now:
-            _, kind, i = events[ev]
-            ev += 1
-            if kind == 0:
-                s = srv.open(plan, C, hop)
-                o = int(rng.integers(0, T - W))
-                s.push(pool[:, o:o + W - hop])  # history: the window minus one hop
-                sess[i], offs[i] = s, o + W - hop
-                outstanding[i] = 0
-                heapq.heappush(hop_times, (now + sched[i][2], i))
-            elif i in sess:
-                s = sess.pop(i)
-                s.close()
-        while hop_times and hop_times[0][0] <= now:
-            t_h, i = heapq.heappop(hop_times)
-            if i not in sess:
-                continue
-            o = offs[i]
-            if o + hop > T:
-                o = 0
-            if sess[i].push(pool[:, o:o + hop]):
-                outstanding[i] += 1
-                pushed += 1
-            offs[i] = o + hop
-            heapq.heappush(hop_times, (t_h + hop_s, i))
-        if now - last_drain > 0.005:
-            drain()
-            last_drain = now
-        nt = min(hop_times[0][0] if hop_times else now + 0.001,
-                 events[ev][0] if ev < len(events) else now + 0.001)
-        if nt > now:
-            time.sleep(min(nt - now, 0.001))
-    srv.flush()
-    drain()
+    # The producer loop is Python: a full garbage collection in a process
+    # with torch loaded takes 35-50 ms, which would hold back every push and
+    # poll and hand the server a burst of hops afterwards.  The collector is
+    # paused for the run (its long-lived objects frozen first).
+    import gc
+    gc.collect()
+    gc.freeze()
+    gc.disable()
+    t0 = time.perf_counter()  # the schedule starts now
+    t0_ns = now_ns()
+    try:
+        while True:
+            now = time.perf_counter() - t0
+            if now >= seconds:
+                break
+            while ev < len(events) and events[ev][0] <= now:
+                _, kind, i = events[ev]
+                ev += 1
+                if kind == 0:
+                    s = srv.open(plan, C, hop)
+                    o = int(rng.integers(0, T - W))
+                    s.push(pool[:, o:o + W - hop])  # history: the window minus one hop
+                    sess[i], offs[i] = s, o + W - hop
+                    outstanding[i] = 0
+                    heapq.heappush(hop_times, (now + sched[i][2], i))
+                elif i in sess:
+                    s = sess.pop(i)
+                    s.close()
+            while hop_times and hop_times[0][0] <= now:
+                t_h, i = heapq.heappop(hop_times)
+                if i not in sess:
+                    continue
+                o = offs[i]
+                if o + hop > T:
+                    o = 0
+                if sess[i].push(pool[:, o:o + hop]):
+                    outstanding[i] += 1
+                    pushed += 1
+                offs[i] = o + hop
+                heapq.heappush(hop_times, (t_h + hop_s, i))
+            if now - last_drain > 0.005:
+                drain()
+                last_drain = now
+            nt = min(hop_times[0][0] if hop_times else now + 0.001,
+                     events[ev][0] if ev < len(events) else now + 0.001)
+            if nt > now:
+                time.sleep(min(nt - now, 0.001))
+        srv.flush()
+        drain()
+    finally:
+        gc.enable()
+        gc.unfreeze()
     st = srv.stats()
     elapsed = time.perf_counter() - t0
     for s in list(sess.values()):
@@ -443,6 +457,22 @@ def bench_stream(n_sessions, C, sfreq, win_s, hop_s, seconds, seed, max_batch, d
     lat = np.array(lat)
     lat_t = np.array(lat_t)
     steady = lat[lat_t >= 2.0] if lat.size else lat
+    # Hops slower than 5 ms, grouped into clusters of nearby push times, each
+    # with the session arrivals and departures just before or during it.
+    slow = np.nonzero(lat > 5.0)[0] if lat.size else np.zeros(0, int)
+    clusters = []
+    if slow.size:
+        order = slow[np.argsort(lat_t[slow])]
+        start = 0
+        for j in range(1, order.size + 1):
+            if j == order.size or lat_t[order[j]] - lat_t[order[j - 1]] > 0.1:
+                idx = order[start:j]
+                t_a, t_b = float(lat_t[idx].min()), float(lat_t[idx].max())
+                near = [k for (t, k, _) in events if t_a - 0.2 <= t <= t_b + 0.05]
+                clusters.append({"t_s": round(t_a, 3), "span_ms": round((t_b - t_a) * 1e3, 1),
+                                 "hops": int(idx.size), "max_ms": round(float(lat[idx].max()), 2),
+                                 "opens": near.count(0), "closes": near.count(2)})
+                start = j
     worst_s = None
     if lat.size:
         sec = np.floor(lat_t).astype(int)
@@ -463,6 +493,10 @@ def bench_stream(n_sessions, C, sfreq, win_s, hop_s, seconds, seed, max_batch, d
         "worst_second_p99": worst_s,
         "results": int(lat.size), "hops_pushed": pushed, "hops_per_s": pushed / elapsed,
         "batches": st["batches"], "mean_batch": st["hops"] / max(1, st["batches"]),
+        "max_batch_hops": st["max_batch_hops"], "max_batch_ms": st["max_batch_ns"] * 1e-6,
+        "slot_waits": st["slot_waits"],
+        "slow_hops": {"over_ms": 5.0, "count": int(slow.size), "clusters": len(clusters),
+                      "worst_clusters": sorted(clusters, key=lambda c: -c["hops"])[:8]},
         "seconds": seconds, "max_batch": max_batch, "deadline_us": deadline_us}
 
 

@@ -462,6 +462,10 @@ typedef struct cwt_server_stats {
     uint64_t sessions_open;
     uint64_t hbm_bytes_used;  /* device bytes held by rings and batch workspaces   */
     uint64_t hbm_budget_bytes;
+    uint64_t max_batch_hops;  /* most hops taken into one launch                   */
+    uint64_t max_batch_ns;    /* longest time from a batch's formation to its
+                                 completion (host clock, staging copy included)    */
+    uint64_t slot_waits;      /* times the launcher waited for a free staging slot */
 } cwt_server_stats;
 
 int cwt_server_opts_init(cwt_server_opts *opts);

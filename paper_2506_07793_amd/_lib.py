@@ -96,7 +96,7 @@ class ServerOpts(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "batches", "hops", "results", "rejected", "sessions_open", "hbm_bytes_used",
-        "hbm_budget_bytes")]
+        "hbm_budget_bytes", "max_batch_hops", "max_batch_ns", "slot_waits")]
 
 
 class BatchItem(ctypes.Structure):

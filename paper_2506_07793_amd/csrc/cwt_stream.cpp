@@ -113,6 +113,7 @@ struct Result {
 struct InFlight {
     StreamClass *cls;
     int slot;
+    uint64_t t_formed;  // host clock when the batch was taken from the queue
     struct Hop {
         cwt_session *s;
         uint64_t hop_idx, t_push;
@@ -345,6 +346,7 @@ void launcher_main(cwt_server *srv)
             for (int i = 0; i < kSlots; ++i)
                 if (!cls->st[i].busy) slot = i;
             if (slot >= 0 || srv->error != CWT_OK) break;
+            srv->stats.slot_waits++;
             srv->cv_done.wait(lk);
             if (srv->pending.empty() || srv->pending.front().s->cls != cls) break;
         }
@@ -354,6 +356,7 @@ void launcher_main(cwt_server *srv)
         InFlight fl;
         fl.cls = cls;
         fl.slot = slot;
+        fl.t_formed = cwt_now_ns();
         int rc = srv->error;
         if (rc == CWT_OK) {
             cls->st[slot].busy = true;
@@ -414,6 +417,8 @@ void completer_main(cwt_server *srv)
         }
         srv->stats.batches++;
         srv->stats.hops += fl.hops.size();
+        srv->stats.max_batch_hops = std::max<uint64_t>(srv->stats.max_batch_hops, fl.hops.size());
+        srv->stats.max_batch_ns = std::max<uint64_t>(srv->stats.max_batch_ns, t_done - fl.t_formed);
         st.busy = false;
         srv->flight.pop_front();
         srv->cv_done.notify_all();

@@ -422,3 +422,34 @@ def test_plan_memory_options_validated_without_gpu():
     assert lib.cwt_plan_describe(ctypes.byref(d), 100, 1000.0, fp, 1, None, 7.0,
                                  ctypes.byref(o)) == _lib.CWT_OK
     assert d.max_channels == 32 and d.device_bytes == 0
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every ctypes mirror of a public struct has the C compiler's size and
+    field offsets for include/cwt.h (a field added on one side only would
+    shift every later field)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"cwt_plan_opts": _lib.PlanOpts, "cwt_plan_desc": _lib.PlanDesc,
+               "cwt_server_opts": _lib.ServerOpts, "cwt_server_stats": _lib.ServerStats,
+               "cwt_batch_item": _lib.BatchItem, "cwt_tune_result": _lib.TuneResult}
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "cwt.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                 text=True).stdout.splitlines())
+    for cname, py in mirrors.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(got["%s.%s" % (cname, fname)]) == getattr(py, fname).offset, (cname, fname)
