@@ -66,6 +66,13 @@ enum cwt_pad {
     CWT_PAD_LINEAR = 4
 };
 enum cwt_out { CWT_OUT_COMPLEX64 = 0, CWT_OUT_POWER_F32 = 1, CWT_OUT_BANDPOWER_F32 = 2 };
+/* Split precision (padded length 4096 only): the radix-16 stages of both the
+ * forward transform of the channels (cwt_forward_spectra, cwt_execute) and
+ * the inverse transforms (cwt_transform_spectra, cwt_execute) run as
+ * DFT-as-GEMM on MFMA with each operand split into a high and a low
+ * half-precision part, three products accumulated in FP32; twiddles and the
+ * spectral multiply stay in FP32.  Other lengths: CWT_E_UNSUPPORTED at plan
+ * creation. */
 enum cwt_precision {
     CWT_PREC_FP32 = 0,       /* FP32 radix-2/3/4/5/7/8/16 FFT in LDS               */
     CWT_PREC_SPLIT_F16 = 1,  /* DFT-as-GEMM radix stages on FP16 MFMA, hi+lo split  */

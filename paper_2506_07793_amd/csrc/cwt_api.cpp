@@ -866,6 +866,8 @@ extern "C" int cwt_forward_spectra(const cwt_plan *P, const float *x, int64_t C,
     resolve_ws(P, ws, ws_bytes);
     int rc = check_exec_args(P, x, true, C, nullptr, false, ws, ws_bytes);
     if (rc != CWT_OK || C == 0) return rc;
+    if (P->opts.precision != CWT_PREC_FP32)
+        return enqueue_forward_split(*P, x, C, P->n, ws, (hipStream_t)stream);
     return enqueue_forward(*P, x, C, P->n, ws, (hipStream_t)stream);
 }
 

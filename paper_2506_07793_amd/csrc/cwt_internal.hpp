@@ -119,6 +119,8 @@ int prepare_split_precision(cwt_plan &P, hipStream_t s);
 void release_split_precision(cwt_plan &P);
 
 size_t split_workspace_bytes(const cwt_plan &P, int64_t C);
+int enqueue_forward_split(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride,
+                          void *ws, hipStream_t s);
 int enqueue_execute_split(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride,
                           void *out, void *ws, hipStream_t s);
 int enqueue_transform_split(const cwt_plan &P, int64_t C, void *out, void *ws, hipStream_t s);

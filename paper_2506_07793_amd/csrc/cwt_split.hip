@@ -12,7 +12,8 @@
 // keeps FP32's exponent range and is not scaled.  Twiddles are applied in
 // FP32 on the VALU when a stage stores its outputs; the DFT constants and
 // twiddles are FP64 values rounded once (the plan's twiddle table).  The
-// forward transform of the channels is the FP32 path's.
+// forward transform of the channels (two real channels per complex
+// transform) runs as the same three stages with the conjugate matrices.
 #include "cwt_internal.hpp"
 #include "fft_core.hpp"
 
@@ -70,6 +71,71 @@ __device__ __forceinline__ int fp16_exponent(float m)
     return 15 - __builtin_amdgcn_frexp_expf(m);
 }
 
+// DFT-16 operands of lane (n, q): row m = n, columns k = 8 q + i of
+// [[Fr, -Fi], [Fi, Fr]] with F[m][r] = exp(SIGN 2 pi i m r / 16), from the
+// 16th roots of unity of the twiddle table (FP64 values rounded once), split
+// into high and low parts.
+template <int SIGN, class Ops>
+__device__ __forceinline__ void dft16_operands(const cf *root16, int n, int q,
+                                               typename Ops::vec &ar_hi, typename Ops::vec &ar_lo,
+                                               typename Ops::vec &ai_hi, typename Ops::vec &ai_lo)
+{
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int k = 8 * q + i;
+        const int r = k & 15;
+        const cf w = root16[(n * r) & 15];
+        const float wy = SIGN > 0 ? w.y : -w.y;
+        // columns 0..15 multiply Xr, 16..31 multiply Xi
+        const float fr = (k < 16) ? w.x : -wy;
+        const float fi = (k < 16) ? wy : w.x;
+        typename Ops::scalar h, l;
+        Ops::split(fr, h, l);
+        ar_hi[i] = h;
+        ar_lo[i] = l;
+        Ops::split(fi, h, l);
+        ai_hi[i] = h;
+        ai_lo[i] = l;
+    }
+}
+
+// The 16-point DFTs of 16 butterflies as split-precision MFMAs: v holds this
+// lane's 8 inputs (lane (n, q): butterfly n, real parts of inputs 8 q .. 8 q + 7
+// for q < 2, imaginary parts of inputs 8 (q - 2) .. for q >= 2).  On return
+// zr / zi hold outputs 4 q .. 4 q + 3 of butterfly n, scaled by 2^e (FP16:
+// the butterfly's largest input magnitude scaled into [2^14, 2^15)).
+template <class Ops>
+__device__ __forceinline__ void dft16_mfma(const float *v, typename Ops::vec ar_hi,
+                                           typename Ops::vec ar_lo, typename Ops::vec ai_hi,
+                                           typename Ops::vec ai_lo, f4 &zr, f4 &zi, int &e)
+{
+    e = 0;
+    if (Ops::kScale) {
+        float m = 0.f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(v[i]));
+        m = fmaxf(m, __shfl_xor(m, 16));
+        m = fmaxf(m, __shfl_xor(m, 32));
+        e = fp16_exponent(m);
+    }
+    typename Ops::vec bh, bl;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        typename Ops::scalar h, l;
+        Ops::split(ldexpf(v[i], e), h, l);
+        bh[i] = h;
+        bl[i] = l;
+    }
+    zr = f4{0.f, 0.f, 0.f, 0.f};
+    zi = f4{0.f, 0.f, 0.f, 0.f};
+    zr = Ops::mfma(ar_hi, bh, zr);
+    zr = Ops::mfma(ar_hi, bl, zr);
+    zr = Ops::mfma(ar_lo, bh, zr);
+    zi = Ops::mfma(ai_hi, bh, zi);
+    zi = Ops::mfma(ai_hi, bl, zi);
+    zi = Ops::mfma(ai_lo, bh, zi);
+}
+
 }  // namespace
 
 // Four workgroups (four waves per SIMD) per CU: the register budget this
@@ -80,7 +146,6 @@ __global__ void __launch_bounds__(kT, 4) k_split_main(MainParams p)
 {
     typedef SplitOps<PREC> Ops;
     typedef typename Ops::vec vec;
-    typedef typename Ops::scalar sc;
     __shared__ cf lds[kL];
     __shared__ cf root16[16];  // exp(2 pi i e / 16), from the twiddle table
     float *ldsf = reinterpret_cast<float *>(lds);
@@ -93,25 +158,8 @@ __global__ void __launch_bounds__(kT, 4) k_split_main(MainParams p)
     if (tid < 16) root16[tid] = tw[tid * (kL / 16)];
     __syncthreads();
 
-    // DFT operands of this lane: row m = n, columns k = 8 q + i, from the
-    // 16th roots of unity of the twiddle table (FP64 values rounded once).
     vec ar_hi, ar_lo, ai_hi, ai_lo;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int k = 8 * q + i;
-        const int r = k & 15;
-        const cf w = root16[(n * r) & 15];
-        // columns 0..15 multiply Xr, 16..31 multiply Xi
-        const float fr = (k < 16) ? w.x : -w.y;
-        const float fi = (k < 16) ? w.y : w.x;
-        sc h, l;
-        Ops::split(fr, h, l);
-        ar_hi[i] = h;
-        ar_lo[i] = l;
-        Ops::split(fi, h, l);
-        ai_hi[i] = h;
-        ai_lo[i] = l;
-    }
+    dft16_operands<1, Ops>(root16, n, q, ar_hi, ar_lo, ai_hi, ai_lo);
 
     const int c = blockIdx.x / p.n_rows;
     const int row = blockIdx.x - c * p.n_rows;
@@ -212,33 +260,7 @@ __global__ void __launch_bounds__(kT, 4) k_split_main(MainParams p)
                         v[i] = ldsf[2 * idx + (q >> 1)];
                     }
                 }
-                int e = 0;
-                if (Ops::kScale) {
-                    float m = 0.f;
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(v[i]));
-                    m = fmaxf(m, __shfl_xor(m, 16));
-                    m = fmaxf(m, __shfl_xor(m, 32));
-                    e = fp16_exponent(m);
-                }
-                vec bh, bl;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    sc h, l;
-                    Ops::split(ldexpf(v[i], e), h, l);
-                    bh[i] = h;
-                    bl[i] = l;
-                }
-                f4 zr = {0.f, 0.f, 0.f, 0.f}, zi = {0.f, 0.f, 0.f, 0.f};
-                zr = Ops::mfma(ar_hi, bh, zr);
-                zr = Ops::mfma(ar_hi, bl, zr);
-                zr = Ops::mfma(ar_lo, bh, zr);
-                zi = Ops::mfma(ai_hi, bh, zi);
-                zi = Ops::mfma(ai_hi, bl, zi);
-                zi = Ops::mfma(ai_lo, bh, zi);
-                dr[g] = zr;
-                di[g] = zi;
-                ex[g] = e;
+                dft16_mfma<Ops>(v, ar_hi, ar_lo, ai_hi, ai_lo, dr[g], di[g], ex[g]);
             }
             __syncthreads();  // every wave has read this stage's inputs
 #pragma unroll
@@ -278,6 +300,92 @@ __global__ void __launch_bounds__(kT, 4) k_split_main(MainParams p)
                 const int d = 64 * wave + 16 * g + n + 256 * (4 * q + i);
                 if (d < N) orow_band[d] = acc[g][i] * inv_n;
             }
+    }
+}
+
+// Forward transform of two real channels packed as z = x0 + i x1 (zero
+// beyond N), as the same three radix-16 stages with F[k][r] =
+// exp(-2 pi i k r / 16) and conjugated twiddles, then the separation
+// X0 = (Z[b] + conj Z[-b]) / 2, X1 = (Z[b] - conj Z[-b]) / (2i) into the half
+// spectra.
+template <int PREC>
+__global__ void __launch_bounds__(kT, 4) k_split_forward(FwdParams p)
+{
+    typedef SplitOps<PREC> Ops;
+    typedef typename Ops::vec vec;
+    __shared__ cf lds[kL];
+    __shared__ cf root16[16];
+    float *ldsf = reinterpret_cast<float *>(lds);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int n = lane & 15, q = lane >> 4;
+    const int N = p.N;
+    const cf *tw = reinterpret_cast<const cf *>(p.tw);
+
+    if (tid < 16) root16[tid] = tw[tid * (kL / 16)];
+    __syncthreads();
+
+    vec ar_hi, ar_lo, ai_hi, ai_lo;
+    dft16_operands<-1, Ops>(root16, n, q, ar_hi, ar_lo, ai_hi, ai_lo);
+
+    const int c0 = 2 * blockIdx.x;
+    const bool has1 = (c0 + 1) < p.C;
+    // lanes q < 2 read the real parts (channel c0), q >= 2 the imaginary
+    // parts (channel c0 + 1, zero when there is none)
+    const float *xq = p.x + (int64_t)(c0 + ((q >> 1) & (int)has1)) * p.x_stride;
+    const bool live = (q >> 1) == 0 || has1;
+
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int Ns = 1 << (4 * s);
+        f4 dr[4], di[4];
+        int ex[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int j = 64 * wave + 16 * g + n;
+            float v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int r = 8 * (q & 1) + i;
+                const int idx = j + 256 * r;  // Stockham input element (j, r)
+                if (s == 0)
+                    v[i] = (live && idx < N) ? xq[idx] : 0.f;
+                else
+                    v[i] = ldsf[2 * idx + (q >> 1)];
+            }
+            dft16_mfma<Ops>(v, ar_hi, ar_lo, ai_hi, ai_lo, dr[g], di[g], ex[g]);
+        }
+        __syncthreads();  // every wave has read this stage's inputs
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int j = 64 * wave + 16 * g + n;
+            const int jm = j & (Ns - 1);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = 4 * q + i;
+                cf y = mk(ldexpf(dr[g][i], -ex[g]), ldexpf(di[g][i], -ex[g]));
+                const int d = (j - jm) * 16 + jm + k * Ns;  // Stockham output slot
+                if (s < 2) {
+                    // next stage's twiddle, conjugated, on its input element
+                    const int Nn = Ns * 16;
+                    const int jn = d & 255, rn = d >> 8;
+                    const cf w = tw[(jn & (Nn - 1)) * rn * (kL / (Nn * 16))];
+                    y = mul(y, mk(w.x, -w.y));
+                }
+                lds[d] = y;  // the last stage leaves Z in natural order
+            }
+        }
+        __syncthreads();
+    }
+    float2 *X0 = p.Xh + (int64_t)c0 * p.Lh;
+    float2 *X1 = X0 + p.Lh;
+    for (int b = tid; b < p.Lh; b += kT) {
+        const cf z = lds[b];
+        const cf zn = lds[(kL - b) & (kL - 1)];
+        const cf zc = mk(zn.x, -zn.y);
+        const cf sm = add(z, zc), df = sub(z, zc);
+        X0[b] = make_float2(0.5f * sm.x, 0.5f * sm.y);
+        if (has1) X1[b] = make_float2(0.5f * df.y, -0.5f * df.x);
     }
 }
 
@@ -342,10 +450,33 @@ int enqueue_transform_split(const cwt_plan &P, int64_t C, void *out, void *ws, h
     return CWT_OK;
 }
 
+int enqueue_forward_split(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride,
+                          void *ws, hipStream_t s)
+{
+    if (C == 0) return CWT_OK;
+    FwdParams fp{};
+    fp.x = x;
+    fp.C = (int)C;
+    fp.N = (int)P.n;
+    fp.x_stride = x_stride;
+    fp.Xh = reinterpret_cast<float2 *>(ws);
+    fp.Lh = P.L / 2 + 1;
+    fp.tw = P.d_tw;
+    fp.rp = P.rp;
+    const dim3 grid((unsigned)((C + 1) / 2));
+    if (P.opts.precision == CWT_PREC_SPLIT_F16)
+        hipLaunchKernelGGL(k_split_forward<CWT_PREC_SPLIT_F16>, grid, dim3(kT), 0, s, fp);
+    else
+        hipLaunchKernelGGL(k_split_forward<CWT_PREC_SPLIT_BF16>, grid, dim3(kT), 0, s, fp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "split-precision forward launch");
+    return CWT_OK;
+}
+
 int enqueue_execute_split(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride,
                           void *out, void *ws, hipStream_t s)
 {
-    int rc = enqueue_forward(P, x, C, x_stride, ws, s);
+    int rc = enqueue_forward_split(P, x, C, x_stride, ws, s);
     if (rc != CWT_OK) return rc;
     return enqueue_transform_split(P, C, out, ws, s);
 }

@@ -102,3 +102,35 @@ def test_split_band_first_stage(prec):
     print("%s band first stage: e_P=%.3e e_W=%.3e" % (prec, e_P, e_W))
     assert e_P <= BOUND[prec]
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["split_f16", "split_bf16"])
+@pytest.mark.parametrize("C,N", [(3, 4096), (2, 3000)], ids=["odd-C", "zero-padded"])
+def test_split_forward_spectra(prec, C, N):
+    """The forward transform on MFMA: the half spectra of every channel (two
+    real channels per complex transform, the last pair with one channel when
+    C is odd; zero padding from N to 4096) against the FP64 FFT of the
+    padded signal, and against the FP32 path's."""
+    d = synth.eeg_64ch(C=C, N=N)
+    x = d["x"]
+    xt = torch.from_numpy(x).cuda()
+    kw = dict(n_cycles=d["n_cycles"], pad="pow2")
+    plan = cwt.Plan(N, d["sfreq"], d["freqs"], precision=prec, **kw)
+    ref_plan = cwt.Plan(N, d["sfreq"], d["freqs"], **kw)
+    assert plan.L == 4096
+    Lh = plan.L // 2 + 1
+    ws = plan.alloc_workspace(C)
+    ws_ref = ref_plan.alloc_workspace(C)
+    plan.forward_spectra(xt, ws)
+    ref_plan.forward_spectra(xt, ws_ref)
+    torch.cuda.synchronize()
+    got = ws[: C * Lh * 8].view(torch.complex64).reshape(C, Lh).cpu().numpy()
+    f32 = ws_ref[: C * Lh * 8].view(torch.complex64).reshape(C, Lh).cpu().numpy()
+    exact = np.fft.rfft(x.astype(np.float64), n=plan.L, axis=1)
+    scale = np.abs(exact).max(axis=1, keepdims=True)
+    e = float(np.max(np.abs(got - exact) / scale))
+    e32 = float(np.max(np.abs(f32 - exact) / scale))
+    print("%s forward C=%d N=%d: max |err| / peak = %.3e (FP32 path %.3e)" % (prec, C, N, e, e32))
+    assert e <= BOUND[prec] / 10
+    plan.close()
+    ref_plan.close()
