@@ -148,8 +148,21 @@ typedef struct cwt_plan cwt_plan;
  * gmw_beta and gmw_gamma finite and > 0 (GMW); known enum values; for
  * CWT_PAD_EXPLICIT explicit_len >= n; for band output every band has
  * lo < hi and owns at least one frequency, and n_bands <= CWT_MAX_BANDS.
- * A padded length above CWT_MAX_LEN, or whose prime factors are not all in
- * {2, 3, 5, 7}, gives CWT_E_UNSUPPORTED.
+ * A padded length whose prime factors are not all in {2, 3, 5, 7} gives
+ * CWT_E_UNSUPPORTED, unless it is above CWT_MAX_LEN.
+ *
+ * Padded lengths above CWT_MAX_LEN (long recordings) make a segmented plan
+ * (Morlet / Gabor in FP32; otherwise CWT_E_UNSUPPORTED): the output is still
+ * the cyclic transform of period L, computed segment by segment
+ * (overlap-save).  Each segment is a transform of length segment_len <=
+ * CWT_MAX_LEN of the zero-padded signal's samples, taken cyclically over L,
+ * that reach segment_margin beyond its segment_outputs outputs on either
+ * side.  The margin is the widest wavelet's time support (Gaussian envelope
+ * above 1e-8 of its peak), so what a segment misses lies below that.  It
+ * must leave at least 1/8 of a 20480-sample segment, and L is at most 2^30
+ * (CWT_E_UNSUPPORTED otherwise).  Segmented plans run through cwt_execute,
+ * cwt_forward_spectra and cwt_transform_spectra only; the other entry
+ * points give CWT_E_UNSUPPORTED.
  *
  * On success the plan owns device memory for the wavelet spectra (FP64
  * evaluation on the GPU, rounded once to FP32, 1/L folded in, only the bins
@@ -198,6 +211,13 @@ typedef struct cwt_plan_desc {
     int32_t spectrum_complex;/* 1: stored spectra are complex (sampled wavelets)  */
     int64_t max_channels;    /* opts->max_channels (0: no limit)                   */
     int64_t device_bytes;    /* device memory the plan owns (0 before creation)   */
+    int64_t n_segments;      /* segmented plan (L above CWT_MAX_LEN): segments per
+                                channel; 0 for plans transformed in one piece     */
+    int64_t segment_len;     /* transform length of the kernels: L, or each
+                                segment's length (the radix schedule's)           */
+    int64_t segment_outputs; /* outputs each segment contributes                   */
+    int64_t segment_margin;  /* input samples each segment reads on either side
+                                of its outputs (the wavelets' time support)       */
 } cwt_plan_desc;
 
 int cwt_plan_info(const cwt_plan *plan, cwt_plan_desc *desc);

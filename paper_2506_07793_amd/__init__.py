@@ -241,7 +241,8 @@ class Plan:
         _lib.check(lib.cwt_plan_info(self._ptr, ctypes.byref(desc)))
         self.desc = desc
         self.n = int(desc.n)
-        self.L = int(desc.L)
+        self.L = int(desc.L)  # the padded length the transform is defined with
+        self.n_segments = int(desc.n_segments)
         self.n_freqs = int(desc.n_freqs)
         self.n_bands = int(desc.n_bands)
         self.out_rows = int(desc.out_rows)
@@ -268,7 +269,7 @@ class Plan:
         cplx = bool(self.desc.spectrum_complex)
         H = np.empty(max(1, int(self.desc.spectrum_bins)) * (2 if cplx else 1), dtype=np.float32)
         band = np.empty((self.n_freqs, 3), dtype=np.int32)
-        tw = np.empty(2 * self.L, dtype=np.float32)
+        tw = np.empty(2 * int(self.desc.segment_len), dtype=np.float32)
         _lib.check(self._lib.cwt_plan_copy_tables(
             self._ptr, H.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
             band.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),

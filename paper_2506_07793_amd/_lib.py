@@ -78,6 +78,10 @@ class PlanDesc(ctypes.Structure):
         ("spectrum_complex", ctypes.c_int32),
         ("max_channels", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64),
+        ("n_segments", ctypes.c_int64),
+        ("segment_len", ctypes.c_int64),
+        ("segment_outputs", ctypes.c_int64),
+        ("segment_margin", ctypes.c_int64),
     ]
 
 

@@ -21,7 +21,7 @@ SOURCES = ["cwt_api.cpp", "cwt_mem.cpp", "cwt_kernels.hip", "cwt_fixed.hip", "cw
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
+    "-Wall", "-Wshadow", "-Wno-unused-function", "-Wno-unused-command-line-argument",
     "-I" + os.path.join(ROOT, "include"),
 ]
 

@@ -45,6 +45,11 @@ void clear_error() { g_last_error.clear(); }
 
 // ----------------------------------------------------------- planning --
 
+// Segmented plans: the longest padded length accepted, and the segment
+// length used (7-smooth, at most CWT_MAX_LEN).
+constexpr int64_t kMaxSegmentedLen = (int64_t)1 << 30;
+constexpr int64_t kMaxSegmentLen = 20480;
+
 static bool smooth7(int64_t m)
 {
     if (m < 1) return false;
@@ -472,17 +477,48 @@ int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
         for (int i = 0; i < n_freqs; ++i)
             smax = std::max(smax, P.sigmas[i] / (2.0 * 3.14159265358979323846 * freqs[i]));
         const double S = std::ceil(umax * smax * sfreq) + 1.0;
-        if (!(n + S <= (double)CWT_MAX_LEN))
-            return fail(CWT_E_UNSUPPORTED,
-                        "linear edge mode needs L >= n + %.0f samples, above %d", S,
-                        CWT_MAX_LEN);
+        if (!(n + S <= (double)kMaxSegmentedLen))
+            return fail(CWT_E_UNSUPPORTED, "linear edge mode needs L >= n + %.0f samples", S);
         L = pad_length(n + (int64_t)S, CWT_PAD_SMOOTH7, 0);
     } else {
         L = pad_length(n, o.pad, o.explicit_len);
     }
-    if (L > CWT_MAX_LEN)
-        return fail(CWT_E_UNSUPPORTED, "padded length %lld exceeds the LDS limit %d",
-                    (long long)L, CWT_MAX_LEN);
+    P.L_full = L;
+    P.n_seg = P.seg_B = P.seg_S = 0;
+    if (L > CWT_MAX_LEN) {
+        // Segmented: the wavelets' Gaussian time support bounds the samples
+        // an output depends on (one side: envelope below 1e-8 of its peak
+        // beyond u = sqrt(2 ln 1e8), u = t / s, s = sigma / (2 pi f)), so
+        // segment transforms of length L reproduce the outputs that lie
+        // further than that from their ends (overlap-save).
+        if (gmw)
+            return fail(CWT_E_UNSUPPORTED,
+                        "padded length %lld above %d needs the Gaussian time support of "
+                        "Morlet / Gabor", (long long)L, CWT_MAX_LEN);
+        if (o.precision != CWT_PREC_FP32)
+            return fail(CWT_E_UNSUPPORTED, "split precision is built for padded length 4096");
+        if (L > kMaxSegmentedLen)
+            return fail(CWT_E_UNSUPPORTED, "padded length %lld above %lld", (long long)L,
+                        (long long)kMaxSegmentedLen);
+        const double useg = std::sqrt(2.0 * std::log(1e8));
+        double smax = 0;
+        for (int i = 0; i < n_freqs; ++i)
+            smax = std::max(smax, P.sigmas[i] / (2.0 * 3.14159265358979323846 * freqs[i]));
+        const int64_t S = (int64_t)std::ceil(useg * smax * sfreq) + 1;
+        const int64_t Lmax = kMaxSegmentLen;  // 7-smooth
+        if (Lmax - 2 * S < Lmax / 8)
+            return fail(CWT_E_UNSUPPORTED,
+                        "padded length %lld above %d: the widest wavelet's support (2 x %lld "
+                        "samples) leaves too little of a %lld-sample segment", (long long)L,
+                        CWT_MAX_LEN, (long long)S, (long long)Lmax);
+        const int64_t nseg = (n + (Lmax - 2 * S) - 1) / (Lmax - 2 * S);
+        const int64_t B = (n + nseg - 1) / nseg;
+        const int64_t Ls = pad_length(B + 2 * S, CWT_PAD_SMOOTH7, 0);
+        P.n_seg = (int)nseg;
+        P.seg_B = (int)B;
+        P.seg_S = (int)S;
+        L = Ls;
+    }
     if (!smooth7(L))
         return fail(CWT_E_UNSUPPORTED,
                     "padded length %lld has a prime factor above 7 (use SMOOTH7 or POW2)",
@@ -512,7 +548,7 @@ int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
     // Register-resident kernels serve the lengths that have one, unless the
     // environment variable CWT_GENERIC_ONLY=1 asks for the generic kernel.
     const char *gen = std::getenv("CWT_GENERIC_ONLY");
-    P.use_fixed = fixed_main_available(P.L) && !(gen && gen[0] == '1');
+    P.use_fixed = fixed_main_available(P.L) && !(gen && gen[0] == '1') && P.n_seg == 0;
     const char *var = std::getenv("CWT_FIXED_VARIANT");
     P.variant = var ? std::atoi(var) : 1;
     apply_tuning_cache(P);
@@ -648,8 +684,12 @@ int wait_plan_ready(const cwt_plan &P, hipStream_t s)
 size_t workspace_bytes(const cwt_plan &P, int64_t C)
 {
     const int64_t Lh = P.L / 2 + 1;
-    size_t b = (size_t)C * (size_t)Lh * sizeof(float2);
-    return (b + 255) & ~(size_t)255;
+    const int64_t rows = P.n_seg ? C * P.n_seg : C;
+    size_t b = (size_t)rows * (size_t)Lh * sizeof(float2);
+    b = (b + 255) & ~(size_t)255;
+    // segmented plans: the gathered segment signals after the spectra
+    if (P.n_seg) b += ((size_t)rows * (size_t)P.L * sizeof(float) + 255) & ~(size_t)255;
+    return b;
 }
 
 int enqueue_forward(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride, void *ws,
@@ -661,6 +701,30 @@ int enqueue_forward(const cwt_plan &P, const float *x, int64_t C, int64_t x_stri
     fp.C = (int)C;
     fp.N = (int)P.n;
     fp.x_stride = x_stride;
+    if (P.n_seg) {
+        // segmented: gather the segments (after the spectra in ws), then
+        // transform them as C n_seg channels of L samples
+        const int64_t rows = C * P.n_seg;
+        const size_t spec = ((size_t)rows * (size_t)(P.L / 2 + 1) * sizeof(float2) + 255) &
+                            ~(size_t)255;
+        SegGatherParams g{};
+        g.x = x;
+        g.x_stride = x_stride;
+        g.C = (int)C;
+        g.N = (int)P.n;
+        g.L_full = P.L_full;
+        g.n_seg = P.n_seg;
+        g.B = P.seg_B;
+        g.S = P.seg_S;
+        g.Ls = P.L;
+        g.xs = reinterpret_cast<float *>(static_cast<char *>(ws) + spec);
+        hipError_t e = launch_segment_gather(g, s);
+        if (e != hipSuccess) return hip_fail(e, "segment gather launch");
+        fp.x = g.xs;
+        fp.C = (int)rows;
+        fp.N = P.L;
+        fp.x_stride = P.L;
+    }
     fp.Xh = reinterpret_cast<float2 *>(ws);
     fp.Lh = P.L / 2 + 1;
     fp.tw = P.d_tw;
@@ -701,6 +765,12 @@ int enqueue_transform(const cwt_plan &P, int64_t C, void *out, void *ws, hipStre
     mp.grp_off = P.d_grp_off;
     mp.rp = P.rp;
     mp.variant = P.variant;
+    if (P.n_seg) {
+        mp.C = (int)(C * P.n_seg);
+        mp.seg_n = P.n_seg;
+        mp.seg_B = P.seg_B;
+        mp.seg_S = P.seg_S;
+    }
     const LaunchEvents ev = next_launch_events(P);
     hipError_t e = (P.use_fixed) ? launch_main_fixed(mp, s, ev) : launch_main(mp, s, ev);
     if (e != hipSuccess) return hip_fail(e, "transform launch");
@@ -747,7 +817,11 @@ static void fill_desc(const cwt_plan *P, cwt_plan_desc *d)
 {
     std::memset(d, 0, sizeof *d);
     d->n = P->n;
-    d->L = P->L;
+    d->L = P->n_seg ? P->L_full : P->L;
+    d->n_segments = P->n_seg;
+    d->segment_len = P->L;
+    d->segment_outputs = P->n_seg ? P->seg_B : 0;
+    d->segment_margin = P->n_seg ? P->seg_S : 0;
     d->n_freqs = P->F;
     d->n_bands = P->n_bands;
     d->out = P->opts.out;
@@ -823,7 +897,8 @@ int check_exec_args(const cwt_plan *P, const float *x, bool x_needed, int64_t C,
     const size_t need = cwt_workspace_size(P, C);
     if (ws_bytes < need)
         return fail(CWT_E_INVALID, "workspace too small: %zu < %zu bytes", ws_bytes, need);
-    const int64_t rows = (P->opts.out == CWT_OUT_BANDPOWER_F32) ? P->n_bands : P->F;
+    const int64_t rows = ((P->opts.out == CWT_OUT_BANDPOWER_F32) ? P->n_bands : P->F) *
+                         (P->n_seg ? P->n_seg : 1);
     if (C * rows > (int64_t)INT32_MAX)
         return fail(CWT_E_UNSUPPORTED, "C x rows exceeds the grid limit");
     // one workgroup per output row; a launch holds fewer than 2^32 work-items
@@ -831,7 +906,8 @@ int check_exec_args(const cwt_plan *P, const float *x, bool x_needed, int64_t C,
     const int64_t threads = (P->opts.precision != CWT_PREC_FP32) ? 256
                             : P->use_fixed                       ? P->L / 16
                                                                  : P->rp.threads;
-    if ((C * rows + (C + 1) / 2) * threads >= ((int64_t)1 << 32))
+    const int64_t fwd_blocks = (C * (P->n_seg ? P->n_seg : 1) + 1) / 2;
+    if ((C * rows + fwd_blocks) * threads >= ((int64_t)1 << 32))
         return fail(CWT_E_UNSUPPORTED,
                     "%lld channels x %lld rows x %lld threads exceed one launch; split C",
                     (long long)C, (long long)rows, (long long)threads);

@@ -105,6 +105,10 @@ int validate(const cwt_batch_item *items, int n)
             return fail(CWT_E_INVALID, "items[%d] has a NULL device pointer", i);
         if (it.plan->opts.precision != CWT_PREC_FP32)
             return fail(CWT_E_UNSUPPORTED, "items[%d]: batches run the FP32 path", i);
+        if (it.plan->n_seg)
+            return fail(CWT_E_UNSUPPORTED,
+                        "items[%d]: segmented plans (padded length above %d) run through "
+                        "cwt_execute", i, CWT_MAX_LEN);
         const int64_t rows =
             (it.plan->opts.out == CWT_OUT_BANDPOWER_F32) ? it.plan->n_bands : it.plan->F;
         if (it.C * rows > (int64_t)INT32_MAX)
@@ -336,10 +340,10 @@ extern "C" int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *w
         c.mode = one_row ? (int)P.opts.out : -1;
         c.max_L = std::max(c.max_L, P.L);
         const int rows = (P.opts.out == CWT_OUT_BANDPOWER_F32) ? P.n_bands : P.F;
-        const double rc = row_cost(P);
+        const double per_row = row_cost(P);
         for (int pr = 0; pr < (int)((items[i].C + 1) / 2); ++pr) {
             c.fwd.push_back({i, pr, 0, 1});
-            c.fwd_cost.push_back(rc);
+            c.fwd_cost.push_back(per_row);
         }
         // band-power rows cost their number of frequencies
         auto freqs_in = [&](int r) {
@@ -350,8 +354,8 @@ extern "C" int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *w
                 int nr = 0;
                 double cost = 0;
                 while (r + nr < rows &&
-                       (nr == 0 || (!c.rows && cost + freqs_in(r + nr) * rc <= kTaskCost))) {
-                    cost += freqs_in(r + nr) * rc;
+                       (nr == 0 || (!c.rows && cost + freqs_in(r + nr) * per_row <= kTaskCost))) {
+                    cost += freqs_in(r + nr) * per_row;
                     ++nr;
                 }
                 c.main.push_back({i, ch, r, nr});

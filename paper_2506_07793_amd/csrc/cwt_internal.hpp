@@ -23,7 +23,14 @@ struct DevMem {
 struct cwt_plan {
     int64_t n = 0;
     double sfreq = 0;
-    int L = 0;
+    int L = 0;  // transform length of the kernels
+    // Segmented plans (padded lengths above CWT_MAX_LEN): the cyclic
+    // transform of period L_full computed segment by segment with transforms
+    // of length L.  Segment s yields outputs [s seg_B, s seg_B + seg_B) from
+    // the padded signal's samples s seg_B - seg_S .. s seg_B + seg_B + seg_S - 1
+    // (mod L_full); n_seg = 0 for plans that are not segmented.
+    int64_t L_full = 0;
+    int seg_B = 0, seg_S = 0, n_seg = 0;
     int F = 0;
     int n_bands = 0;
     int device = 0;

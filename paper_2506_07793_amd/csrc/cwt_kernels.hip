@@ -339,7 +339,20 @@ __device__ __forceinline__ void main_task(const P &p, int c, int row)
     }
     const gptr<cf> X = as_global(reinterpret_cast<const cf *>(p.Xh) + (int64_t)c * Lh);
 
-    float *orow_band = reinterpret_cast<float *>(p.out) + ((int64_t)c * p.n_rows + row) * N;
+    // Output channel and the samples this row stores: [0, N), or for a
+    // segment of a segmented plan its middle seg_B samples, shifted to the
+    // segment's place in the output row.
+    int oc = c, t_first = 0, t_count = N;
+    int64_t shift = 0;
+    if (p.seg_n > 0) {
+        const int sg = c % p.seg_n;
+        oc = c / p.seg_n;
+        t_first = p.seg_S;
+        t_count = max(0, min(p.seg_B, N - sg * p.seg_B));
+        shift = (int64_t)sg * p.seg_B - p.seg_S;
+    }
+    float *orow_band =
+        reinterpret_cast<float *>(p.out) + ((int64_t)oc * p.n_rows + row) * N + shift;
     const float inv_n = 1.0f / (float)(qe - qb);
 
     auto lds_load = [](int idx) -> cf { return lds[idx]; };
@@ -375,16 +388,16 @@ __device__ __forceinline__ void main_task(const P &p, int c, int row)
         // Output row of this frequency (band mode: of the band, accumulated
         // over its frequencies; only this workgroup touches it, and every
         // thread revisits the same samples t for each frequency, so it reads
-        // back its own earlier writes).  The store functor carries five
-        // registers (row pointer, n, flags, 1/count) so that it is passed to
-        // the out-of-line last pass in registers rather than through memory.
+        // back its own earlier writes).  The store functor is kept to six
+        // registers (row pointer, first sample, count, flags, 1/count).
         const gptr_mut<float> orow = as_global_mut(
-            (MODE == kOutBand) ? orow_band
-                               : reinterpret_cast<float *>(p.out) +
-                                     ((int64_t)c * p.n_rows + f) * N * (MODE == kOutComplex ? 2 : 1));
+            (MODE == kOutBand)
+                ? orow_band
+                : reinterpret_cast<float *>(p.out) +
+                      (((int64_t)oc * p.n_rows + f) * N + shift) * (MODE == kOutComplex ? 2 : 1));
         const int eflags = (q == qb ? 1 : 0) | (q == qe - 1 ? 2 : 0);
-        auto epi = [orow, N, eflags, inv_n](int, int t, cf v) {
-            if (t < N) {
+        auto epi = [orow, t_first, t_count, eflags, inv_n](int, int t, cf v) {
+            if ((unsigned)(t - t_first) < (unsigned)t_count) {
                 const float pw = v.x * v.x + v.y * v.y;
                 if (MODE == kOutComplex) {
                     reinterpret_cast<gptr_mut<f2_t>>(orow)[t] = f2_t{v.x, v.y};
@@ -679,6 +692,34 @@ static hipError_t launch_main_t(const MainParams &p, hipStream_t s, LaunchEvents
     set_lds_limit((const void *)k_main<MAXV, MODE>, lds);
     hipExtLaunchKernelGGL((k_main<MAXV, MODE>), dim3(blocks), dim3(p.rp.threads), lds, s,
                           ev.start, ev.stop, 0, p);
+    return hipGetLastError();
+}
+
+// Segment inputs of a segmented plan: row c n_seg + s of xs (length Ls) is
+// the zero-padded signal's samples s B - S .. s B - S + Ls - 1, indices taken
+// modulo the cyclic period L_full (samples at or beyond N are zero).
+__global__ void k_segment_gather(SegGatherParams p)
+{
+    const int64_t total = (int64_t)p.C * p.n_seg * p.Ls;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = e / p.Ls;
+        const int t = (int)(e - row * p.Ls);
+        const int64_t c = row / p.n_seg;
+        const int sg = (int)(row - c * p.n_seg);
+        int64_t i = ((int64_t)sg * p.B - p.S + t) % p.L_full;
+        if (i < 0) i += p.L_full;
+        p.xs[e] = (i < p.N) ? p.x[c * p.x_stride + i] : 0.f;
+    }
+}
+
+hipError_t launch_segment_gather(const SegGatherParams &p, hipStream_t s)
+{
+    const int64_t total = (int64_t)p.C * p.n_seg * p.Ls;
+    if (total == 0) return hipSuccess;
+    const int64_t want = (total + 255) / 256;
+    const int blocks = (int)(want < 65536 ? want : 65536);
+    hipLaunchKernelGGL(k_segment_gather, dim3(blocks), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 

@@ -57,6 +57,11 @@ struct MainParams {
                            // [n_bands] band indices by frequency count, largest first
     RadixPlan rp;
     int variant;           // register-resident kernel: 0 table twiddles, 1 power twiddles
+    // Segmented plans (runtime-radix kernel only): the C channels are
+    // channel x segment rows, seg_n segments per channel; segment s stores its
+    // samples [seg_S, seg_S + seg_B) at s seg_B .. of the output row (N long).
+    // seg_n = 0: not segmented.
+    int seg_n, seg_B, seg_S;
 };
 
 // ------------------------------------------------------------- batched --
@@ -160,6 +165,16 @@ hipError_t launch_generate(const GenParams &p, int total_bins, hipStream_t s);
 // ((j - c) mod L) / L) in FP64, rounded once; roots: [L] FP64 scratch.
 hipError_t launch_user_spectra(const float2 *w, int F, int wl, int c, int L, double2 *roots,
                                float2 *Hd, hipStream_t s);
+// Segment inputs of a segmented plan (see MainParams::seg_n).
+struct SegGatherParams {
+    const float *x;    // [C][N] signal, x_stride elements between channels
+    int64_t x_stride;
+    int C, N;
+    int64_t L_full;    // cyclic period
+    int n_seg, B, S, Ls;
+    float *xs;         // [C n_seg][Ls]
+};
+hipError_t launch_segment_gather(const SegGatherParams &p, hipStream_t s);
 hipError_t launch_forward(const FwdParams &p, hipStream_t s);
 hipError_t launch_main(const MainParams &p, hipStream_t s, LaunchEvents ev = {});
 // Register-resident kernels for the padded lengths that have one.

@@ -62,6 +62,10 @@ extern "C" int cwt_execute_noalloc(const cwt_plan *P, const float *x, int64_t C,
 {
     clear_error();
     if (!P) return fail(CWT_E_INVALID, "cwt_execute_noalloc: plan is NULL");
+    if (P->n_seg)
+        return fail(CWT_E_UNSUPPORTED,
+                    "segmented plans (padded length above %d) run through cwt_execute",
+                    CWT_MAX_LEN);
     if (C < 0 || C > (int64_t)1 << 24) return fail(CWT_E_INVALID, "C out of range");
     if (C == 0) return CWT_OK;
     const size_t need = cwt_workspace_size(P, C);

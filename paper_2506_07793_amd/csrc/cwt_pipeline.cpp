@@ -65,6 +65,10 @@ extern "C" int cwt_execute_batches(const cwt_plan *P, const float *x, int64_t x_
 {
     clear_error();
     if (!P) return fail(CWT_E_INVALID, "cwt_execute_batches: plan is NULL");
+    if (P->n_seg)
+        return fail(CWT_E_UNSUPPORTED,
+                    "segmented plans (padded length above %d) run through cwt_execute",
+                    CWT_MAX_LEN);
     if (n_batches < 0) return fail(CWT_E_INVALID, "n_batches %d < 0", (int)n_batches);
     if (x_batch_stride < 0 || out_batch_stride < 0)
         return fail(CWT_E_INVALID, "negative batch stride");

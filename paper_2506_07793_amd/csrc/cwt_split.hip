@@ -150,8 +150,6 @@ __global__ void __launch_bounds__(kT, 4) k_split_main(MainParams p)
     __shared__ cf root16[16];  // exp(2 pi i e / 16), from the twiddle table
     float *ldsf = reinterpret_cast<float *>(lds);
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int n = lane & 15, q = lane >> 4;
     const int N = p.N;
     const cf *tw = reinterpret_cast<const cf *>(p.tw);
 
@@ -159,7 +157,7 @@ __global__ void __launch_bounds__(kT, 4) k_split_main(MainParams p)
     __syncthreads();
 
     vec ar_hi, ar_lo, ai_hi, ai_lo;
-    dft16_operands<1, Ops>(root16, n, q, ar_hi, ar_lo, ai_hi, ai_lo);
+    dft16_operands<1, Ops>(root16, tid & 15, (tid & 63) >> 4, ar_hi, ar_lo, ai_hi, ai_lo);
 
     const int c = blockIdx.x / p.n_rows;
     const int row = blockIdx.x - c * p.n_rows;
@@ -297,7 +295,7 @@ __global__ void __launch_bounds__(kT, 4) k_split_main(MainParams p)
         for (int g = 0; g < 4; ++g)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int d = 64 * wave + 16 * g + n + 256 * (4 * q + i);
+                const int d = 64 * (tid >> 6) + 16 * g + (tid & 15) + 256 * (4 * ((tid & 63) >> 4) + i);
                 if (d < N) orow_band[d] = acc[g][i] * inv_n;
             }
     }

@@ -541,6 +541,9 @@ extern "C" int cwt_stream_open(cwt_server *srv, const cwt_plan *plan, int64_t C,
         return fail(CWT_E_INVALID, "stream sessions need a plan with CWT_OUT_BANDPOWER_F32");
     if (plan->opts.precision != CWT_PREC_FP32)
         return fail(CWT_E_UNSUPPORTED, "stream sessions run the FP32 path");
+    if (plan->n_seg)
+        return fail(CWT_E_UNSUPPORTED, "stream windows must fit one transform (n <= %d)",
+                    CWT_MAX_LEN);
     if (plan->user)
         return fail(CWT_E_UNSUPPORTED,
                     "stream sessions need a closed-form wavelet (plans from sampled wavelets "

@@ -120,6 +120,9 @@ extern "C" int cwt_plan_autotune(cwt_plan *P, int64_t C, void *stream, cwt_tune_
     if (C < 1) return fail(CWT_E_INVALID, "C must be >= 1");
     if (res) std::memset(res, 0, sizeof *res);
     if (P->opts.precision != CWT_PREC_FP32) return CWT_OK;
+    if (P->n_seg)
+        return fail(CWT_E_UNSUPPORTED,
+                    "segmented plans (padded length above %d) are not autotuned", CWT_MAX_LEN);
     hipStream_t s = (hipStream_t)stream;
     const int64_t Ct = C < 16 ? C : 16;
     const int64_t rows = (P->opts.out == CWT_OUT_BANDPOWER_F32) ? P->n_bands : P->F;

@@ -171,7 +171,9 @@ def test_validation_errors():
     _expect(INV, freqs=f, n_cycles=5.0, pad="explicit", explicit_len=100)  # < n
     _expect(INV, freqs=f, n_cycles=5.0, out="bandpower", bands=[(30.0, 40.0)])  # owns none
     _expect(INV, freqs=f, n_cycles=5.0, out="bandpower", bands=[(20.0, 10.0)])
-    _expect(UNS, n=20481)                                                   # beyond LDS
+    _expect(UNS, n=20481, wavelet="gmw", n_cycles=None)                     # segmented GMW
+    _expect(UNS, n=20481, precision="split_f16")                            # segmented split
+    _expect(UNS, n=(1 << 30) + 1)                                           # beyond 2^30
     _expect(UNS, n=1009, pad="none")                                        # prime length
     _expect(UNS, n=100, pad="explicit", explicit_len=121)                   # 11^2
 
@@ -305,9 +307,49 @@ def test_linear_edge_mode_length():
     with pytest.raises(cwt.CwtError) as e:
         cwt.describe(2000, 1000.0, [10.0], wavelet="gmw", pad="linear")
     assert e.value.code == _lib.CWT_E_UNSUPPORTED
+    # linear edges beyond one transform: a segmented plan of the same L ...
+    d = cwt.describe(20000, 1000.0, [2.0], n_cycles=[5.0], pad="linear")
+    S = oracle.linear_support(1000.0, [2.0], [5.0])
+    assert d.L == oracle.pad_length(20000, "linear", support=S) and d.n_segments >= 2
+    # ... unless the wavelet's support leaves too little of a segment
     with pytest.raises(cwt.CwtError) as e:
         cwt.describe(20000, 1000.0, [0.5], n_cycles=[10.0], pad="linear")
     assert e.value.code == _lib.CWT_E_UNSUPPORTED
+
+
+def _smooth7(m):
+    for p in (2, 3, 5, 7):
+        while m % p == 0:
+            m //= p
+    return m == 1
+
+
+@pytest.mark.parametrize("n,pad,sfreq,fmin", [(50000, "smooth7", 1000.0, 1.0),
+                                              (20481, "smooth7", 1000.0, 1.0),
+                                              (40009, "none", 500.0, 2.0),
+                                              (300000, "smooth7", 1000.0, 1.0),
+                                              (30000, "linear", 2048.0, 4.0)])
+def test_segmented_plan_geometry(n, pad, sfreq, fmin):
+    """Padded lengths above 20480: L is the padded length of the pad mode (the
+    cyclic period of the result), and the segments tile [0, n): each has
+    segment_outputs outputs and reads segment_margin samples on either side,
+    the margin being the widest wavelet's time support at 1e-8 of the
+    envelope's peak; the segment transform is 7-smooth and at most 20480."""
+    import math
+    import oracle
+    freqs = synth.log_freqs(fmin, min(100.0, 0.4 * sfreq), 60)
+    cyc = synth.eeg_cycles(freqs)
+    d = cwt.describe(n, sfreq, freqs, n_cycles=cyc, pad=pad)
+    sup = oracle.linear_support(sfreq, freqs, cyc) if pad == "linear" else None
+    L = oracle.pad_length(n, pad, support=sup)
+    assert d.L == L and d.n == n
+    assert d.n_segments >= 2
+    S = math.ceil(math.sqrt(2 * math.log(1e8)) * max(cyc / (2 * math.pi * freqs)) * sfreq) + 1
+    assert d.segment_margin == S
+    B, Ls = d.segment_outputs, d.segment_len
+    assert (d.n_segments - 1) * B < n <= d.n_segments * B
+    assert B + 2 * S <= Ls <= 20480 and _smooth7(Ls)
+    assert d.kernel == 0  # the runtime-radix kernel runs the segments
 
 
 def test_sampled_wavelet_plan_validation_without_gpu():
