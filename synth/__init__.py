@@ -47,17 +47,23 @@ def pink_noise(rng, C, N, rms=EEG_RMS_UV):
 
 
 def alpha_bursts(rng, C, N, sfreq, rate_hz=1.0, env_sd_s=0.15, peak=EEG_RMS_UV, f=10.0):
-    """10 Hz bursts: Poisson onsets at rate_hz, Gaussian envelope, random phase."""
+    """10 Hz bursts: Poisson onsets at rate_hz, Gaussian envelope, random phase.
+    Each burst is evaluated within 8 envelope widths of its centre (beyond,
+    its envelope is below exp(-32) of the peak)."""
     t = np.arange(N) / float(sfreq)
     dur = N / float(sfreq)
+    half = int(np.ceil(8.0 * env_sd_s * sfreq))
     out = np.zeros((C, N))
     for c in range(C):
         n_b = rng.poisson(rate_hz * dur)
         for _ in range(n_b):
             t0 = rng.uniform(0.0, dur)
             ph = rng.uniform(0.0, 2.0 * np.pi)
-            out[c] += peak * np.exp(-0.5 * ((t - t0) / env_sd_s) ** 2) * np.cos(
-                2.0 * np.pi * f * (t - t0) + ph)
+            i = int(t0 * sfreq)
+            a, b = max(0, i - half), min(N, i + half + 1)
+            tt = t[a:b] - t0
+            out[c, a:b] += peak * np.exp(-0.5 * (tt / env_sd_s) ** 2) * np.cos(
+                2.0 * np.pi * f * tt + ph)
     return out
 
 
