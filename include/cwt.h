@@ -218,6 +218,11 @@ typedef struct cwt_plan_desc {
     int64_t segment_outputs; /* outputs each segment contributes                   */
     int64_t segment_margin;  /* input samples each segment reads on either side
                                 of its outputs (the wavelets' time support)       */
+    int64_t band_chunks;     /* band power on the runtime-radix or split kernels:
+                                transform rows per channel, each band cut into
+                                chunks of at most a quarter of the largest band
+                                (combined by a second launch); 0: one row per
+                                band                                                */
 } cwt_plan_desc;
 
 int cwt_plan_info(const cwt_plan *plan, cwt_plan_desc *desc);

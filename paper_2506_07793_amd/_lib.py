@@ -82,6 +82,7 @@ class PlanDesc(ctypes.Structure):
         ("segment_len", ctypes.c_int64),
         ("segment_outputs", ctypes.c_int64),
         ("segment_margin", ctypes.c_int64),
+        ("band_chunks", ctypes.c_int64),
     ]
 
 

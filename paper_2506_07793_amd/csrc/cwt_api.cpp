@@ -50,6 +50,8 @@ void clear_error() { g_last_error.clear(); }
 constexpr int64_t kMaxSegmentedLen = (int64_t)1 << 30;
 constexpr int64_t kMaxSegmentLen = 20480;
 
+static void set_chunks(cwt_plan &P);
+
 static bool smooth7(int64_t m)
 {
     if (m < 1) return false;
@@ -549,6 +551,7 @@ int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
     // environment variable CWT_GENERIC_ONLY=1 asks for the generic kernel.
     const char *gen = std::getenv("CWT_GENERIC_ONLY");
     P.use_fixed = fixed_main_available(P.L) && !(gen && gen[0] == '1') && P.n_seg == 0;
+    set_chunks(P);
     const char *var = std::getenv("CWT_FIXED_VARIANT");
     P.variant = var ? std::atoi(var) : 1;
     apply_tuning_cache(P);
@@ -589,6 +592,32 @@ static int dev_upload(cwt_plan &P, T **dst, const T *src, size_t count, hipStrea
     return CWT_OK;
 }
 
+// Band rows on the runtime-radix and split-precision kernels run a band's
+// frequencies one after another in one workgroup; cut into chunks of at most
+// a quarter of the largest band, the longest chain shrinks about 4-fold.
+static void set_chunks(cwt_plan &P)
+{
+    P.n_chunks = 0;
+    P.chunk_table.clear();
+    if (P.opts.out != CWT_OUT_BANDPOWER_F32) return;
+    if (P.use_fixed && P.opts.precision == CWT_PREC_FP32) return;  // sub-group rows instead
+    int biggest = 0;
+    for (int b = 0; b < P.n_bands; ++b)
+        biggest = std::max(biggest, P.grp_off[b + 1] - P.grp_off[b]);
+    const int g = std::max(1, (biggest + 3) / 4);
+    std::vector<int> off{0}, first{0};
+    for (int b = 0; b < P.n_bands; ++b) {
+        const int lo = P.grp_off[b], hi = P.grp_off[b + 1];
+        const int k = (hi - lo + g - 1) / g;  // chunks of this band, sizes differing by <= 1
+        for (int j = 1; j <= k; ++j) off.push_back(lo + (int)((int64_t)(hi - lo) * j / k));
+        first.push_back((int)off.size() - 1);
+    }
+    if ((int)off.size() - 1 == P.n_bands) return;  // one chunk per band: nothing gained
+    P.n_chunks = (int)off.size() - 1;
+    P.chunk_table = off;
+    P.chunk_table.insert(P.chunk_table.end(), first.begin(), first.end());
+}
+
 // The band-power kernels take a band's frequencies one after another in one
 // workgroup, so the band with the most frequencies is the longest job; its
 // workgroups are launched first (longest-processing-time-first order), the
@@ -618,6 +647,7 @@ void free_plan_device(cwt_plan &P, hipStream_t s)
     P.d_Hc = nullptr;
     P.d_tw = nullptr;
     P.d_grp_freq = P.d_grp_off = nullptr;
+    P.d_chunk = nullptr;
 }
 
 int upload_plan(cwt_plan &P, hipStream_t s)
@@ -637,6 +667,10 @@ int upload_plan(cwt_plan &P, hipStream_t s)
         set_group_table(P);
         if ((rc = dev_upload(P, &P.d_grp_off, P.grp_table.data(), P.grp_table.size(), s,
                              "group offs")))
+            return rc;
+        if (P.n_chunks &&
+            (rc = dev_upload(P, &P.d_chunk, P.chunk_table.data(), P.chunk_table.size(), s,
+                             "band chunks")))
             return rc;
     }
     GenParams g{};
@@ -689,7 +723,35 @@ size_t workspace_bytes(const cwt_plan &P, int64_t C)
     b = (b + 255) & ~(size_t)255;
     // segmented plans: the gathered segment signals after the spectra
     if (P.n_seg) b += ((size_t)rows * (size_t)P.L * sizeof(float) + 255) & ~(size_t)255;
+    // band chunks: their partial rows [C][n_chunks][n]
+    if (P.n_chunks)
+        b += ((size_t)C * (size_t)P.n_chunks * (size_t)P.n * sizeof(float) + 255) & ~(size_t)255;
     return b;
+}
+
+float *chunk_partials(const cwt_plan &P, int64_t C, void *ws)
+{
+    const int64_t rows = P.n_seg ? C * P.n_seg : C;
+    size_t off = ((size_t)rows * (size_t)(P.L / 2 + 1) * sizeof(float2) + 255) & ~(size_t)255;
+    if (P.n_seg) off += ((size_t)rows * (size_t)P.L * sizeof(float) + 255) & ~(size_t)255;
+    return reinterpret_cast<float *>(static_cast<char *>(ws) + off);
+}
+
+int enqueue_chunk_reduce(const cwt_plan &P, int64_t C, const float *part, void *out,
+                         hipStream_t s)
+{
+    ChunkReduceParams r{};
+    r.part = part;
+    r.out = static_cast<float *>(out);
+    r.C = (int)C;
+    r.n_chunks = P.n_chunks;
+    r.n_bands = P.n_bands;
+    r.N = (int)P.n;
+    r.chunk_off = P.d_chunk;
+    r.band_first = P.d_chunk + P.n_chunks + 1;
+    hipError_t e = launch_chunk_reduce(r, s);
+    if (e != hipSuccess) return hip_fail(e, "band chunk reduce launch");
+    return CWT_OK;
 }
 
 int enqueue_forward(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride, void *ws,
@@ -771,9 +833,17 @@ int enqueue_transform(const cwt_plan &P, int64_t C, void *out, void *ws, hipStre
         mp.seg_B = P.seg_B;
         mp.seg_S = P.seg_S;
     }
+    float *part = nullptr;
+    if (P.n_chunks) {  // chunk rows into the partial rows, then the band means
+        part = chunk_partials(P, C, ws);
+        mp.out = part;
+        mp.n_rows = P.n_chunks;
+        mp.grp_off = P.d_chunk;
+    }
     const LaunchEvents ev = next_launch_events(P);
     hipError_t e = (P.use_fixed) ? launch_main_fixed(mp, s, ev) : launch_main(mp, s, ev);
     if (e != hipSuccess) return hip_fail(e, "transform launch");
+    if (part) return enqueue_chunk_reduce(P, C, part, out, s);
     return CWT_OK;
 }
 
@@ -822,6 +892,7 @@ static void fill_desc(const cwt_plan *P, cwt_plan_desc *d)
     d->segment_len = P->L;
     d->segment_outputs = P->n_seg ? P->seg_B : 0;
     d->segment_margin = P->n_seg ? P->seg_S : 0;
+    d->band_chunks = P->n_chunks;
     d->n_freqs = P->F;
     d->n_bands = P->n_bands;
     d->out = P->opts.out;

@@ -42,6 +42,15 @@ struct cwt_plan {
     // What d_grp_off holds: grp_off, then the band indices by frequency
     // count, largest first (set by set_group_table)
     std::vector<int> grp_table;
+    // Band power on the runtime-radix and split-precision kernels: each band
+    // is cut into chunks of at most chunk_max frequencies, one transform row
+    // per chunk (its mean |W|^2 into a partial row of the workspace), then
+    // the chunks of a band are combined.  n_chunks = 0: rows are whole bands.
+    // chunk_table: [n_chunks + 1] offsets into grp_freq, then [n_bands + 1]
+    // offsets of each band's first chunk.
+    int n_chunks = 0;
+    std::vector<int> chunk_table;
+    int *d_chunk = nullptr;
     int total_bins = 0;
     int max_bins = 0;
     bool use_fixed = false;  // register-resident kernel for this length
@@ -112,6 +121,11 @@ void plan_free_all(cwt_plan &P, hipStream_t s);
 // Make stream s wait until the plan's tables are written (no-op when they are).
 int wait_plan_ready(const cwt_plan &P, hipStream_t s);
 size_t workspace_bytes(const cwt_plan &P, int64_t C);
+// Band-power chunk rows (P.n_chunks > 0): where the partial rows start in ws.
+float *chunk_partials(const cwt_plan &P, int64_t C, void *ws);
+// Combine the partial rows of each band into out (after a transform launch).
+int enqueue_chunk_reduce(const cwt_plan &P, int64_t C, const float *part, void *out,
+                         hipStream_t s);
 int enqueue_forward(const cwt_plan &P, const float *x, int64_t C, int64_t x_stride, void *ws,
                     hipStream_t s);
 int enqueue_transform(const cwt_plan &P, int64_t C, void *out, void *ws, hipStream_t s);

@@ -723,6 +723,33 @@ hipError_t launch_segment_gather(const SegGatherParams &p, hipStream_t s)
     return hipGetLastError();
 }
 
+__global__ void k_chunk_reduce(ChunkReduceParams p)
+{
+    const int64_t total = (int64_t)p.C * p.n_bands * p.N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = e / p.N;  // c n_bands + b
+        const int t = (int)(e - row * p.N);
+        const int c = (int)(row / p.n_bands), b = (int)(row - (int64_t)c * p.n_bands);
+        const int k0 = p.band_first[b], k1 = p.band_first[b + 1];
+        float acc = 0.f;
+        for (int k = k0; k < k1; ++k)
+            acc += p.part[((int64_t)c * p.n_chunks + k) * p.N + t] *
+                   (float)(p.chunk_off[k + 1] - p.chunk_off[k]);
+        p.out[e] = acc / (float)(p.chunk_off[k1] - p.chunk_off[k0]);
+    }
+}
+
+hipError_t launch_chunk_reduce(const ChunkReduceParams &p, hipStream_t s)
+{
+    const int64_t total = (int64_t)p.C * p.n_bands * p.N;
+    if (total == 0) return hipSuccess;
+    const int64_t want = (total + 255) / 256;
+    const int blocks = (int)(want < 65536 ? want : 65536);
+    hipLaunchKernelGGL(k_chunk_reduce, dim3(blocks), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
 hipError_t launch_main(const MainParams &p, hipStream_t s, LaunchEvents ev)
 {
     if (p.rp.maxv <= 16) {

@@ -175,6 +175,17 @@ struct SegGatherParams {
     float *xs;         // [C n_seg][Ls]
 };
 hipError_t launch_segment_gather(const SegGatherParams &p, hipStream_t s);
+// Band power from chunk rows: out[c][b][t] = sum over the chunks k of band b
+// of part[c][k][t] (the chunk's mean) times its frequency count, over the
+// band's count.
+struct ChunkReduceParams {
+    const float *part;       // [C][n_chunks][N]
+    float *out;              // [C][n_bands][N]
+    int C, n_chunks, n_bands, N;
+    const int *chunk_off;    // [n_chunks + 1] frequency offsets of the chunks
+    const int *band_first;   // [n_bands + 1] first chunk of each band
+};
+hipError_t launch_chunk_reduce(const ChunkReduceParams &p, hipStream_t s);
 hipError_t launch_forward(const FwdParams &p, hipStream_t s);
 hipError_t launch_main(const MainParams &p, hipStream_t s, LaunchEvents ev = {});
 // Register-resident kernels for the padded lengths that have one.

@@ -440,11 +440,19 @@ int enqueue_transform_split(const cwt_plan &P, int64_t C, void *out, void *ws, h
     mp.grp_freq = P.d_grp_freq;
     mp.grp_off = P.d_grp_off;
     mp.rp = P.rp;
+    float *part = nullptr;
+    if (P.n_chunks) {  // chunk rows into the partial rows, then the band means
+        part = chunk_partials(P, C, ws);
+        mp.out = part;
+        mp.n_rows = P.n_chunks;
+        mp.grp_off = P.d_chunk;
+    }
     const LaunchEvents ev = next_launch_events(P);
     hipError_t e = (P.opts.precision == CWT_PREC_SPLIT_F16)
                        ? launch_split_modes<CWT_PREC_SPLIT_F16>(mp, s, ev)
                        : launch_split_modes<CWT_PREC_SPLIT_BF16>(mp, s, ev);
     if (e != hipSuccess) return hip_fail(e, "split-precision transform launch");
+    if (part) return enqueue_chunk_reduce(P, C, part, out, s);
     return CWT_OK;
 }
 

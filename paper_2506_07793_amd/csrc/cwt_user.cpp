@@ -128,6 +128,9 @@ int build_user_plan(cwt_plan &P, const float *wavelets, int64_t w_len, hipStream
         if (rc == CWT_OK)
             rc = upload(P, true, &P.d_grp_off, P.grp_table.data(), P.grp_table.size(), s,
                         "group offs");
+        if (rc == CWT_OK && P.n_chunks)
+            rc = upload(P, true, &P.d_chunk, P.chunk_table.data(), P.chunk_table.size(), s,
+                        "band chunks");
     }
     if (rc != CWT_OK) return rc;
     GenParams g{};  // twiddles only (no closed-form spectra)

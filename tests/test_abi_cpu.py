@@ -495,3 +495,27 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(got[cname]) == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert int(got["%s.%s" % (cname, fname)]) == getattr(py, fname).offset, (cname, fname)
+
+
+@pytest.mark.parametrize("n,F,prec,expect_chunks", [(4096, 100, "fp32", False),
+                                                     (2000, 100, "fp32", True),
+                                                     (4096, 100, "split_f16", True),
+                                                     (2000, 40, "fp32", True),
+                                                     (3000, 5, "fp32", False)])
+def test_band_chunks(n, F, prec, expect_chunks):
+    """Band power on the runtime-radix and split-precision kernels cuts each
+    band into chunks of at most ceil(largest band / 4) frequencies (sizes
+    within one of each other); the register-resident FP32 kernel keeps one
+    row per band, and so does a grid whose bands are all single frequencies."""
+    import oracle
+    # five frequencies: one in each EEG band
+    freqs = np.array([2.0, 6.0, 10.0, 20.0, 50.0]) if F == 5 else synth.log_freqs(1.0, 100.0, F)
+    d = cwt.describe(n, 1000.0, freqs, n_cycles=synth.eeg_cycles(freqs), out="bandpower",
+                     precision=prec)
+    sizes = [len(g) for g in oracle.band_groups(freqs)]
+    g = max(1, -(-max(sizes) // 4))
+    want = sum(-(-s // g) for s in sizes)
+    if expect_chunks:
+        assert want > len(sizes) and d.band_chunks == want, (d.band_chunks, want)
+    else:
+        assert d.band_chunks == 0
