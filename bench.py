@@ -266,6 +266,43 @@ def bench_batch(steps, n_rec=256):
     return res
 
 
+def bench_long_recording(reps=5):
+    """A recording longer than one transform: 5 minutes of 64-channel EEG at
+    1000 Hz (300 000 samples), the 100-frequency grid, power out (7.7 GB),
+    run as a segmented plan (overlap-save over the full padded length).
+    Times `reps` calls of cwt_execute with events."""
+    import torch
+    import paper_2506_07793_amd as cwt
+    import synth
+    n, sfreq, C = 300000, 1000.0, 64
+    d = synth.eeg_64ch(C=1, N=16)
+    x = torch.from_numpy(synth.eeg(C, n, sfreq, 45)).cuda()
+    plan = cwt.Plan(n, sfreq, d["freqs"], n_cycles=d["n_cycles"], out="power")
+    out = plan.alloc_output(C)
+    ws = plan.alloc_workspace(C)
+    plan.execute(x, out=out, ws=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.execute(x, out=out, ws=ws)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    res = {"workload": "64 ch x 300000 samples @1000 Hz, 100 log freqs 1-100 Hz, power out, "
+                       "segmented plan",
+           "padded_len": plan.L, "segments": plan.n_segments,
+           "segment_len": int(plan.desc.segment_len),
+           "segment_outputs": int(plan.desc.segment_outputs),
+           "ms_per_call": ms, "samples_freqs_per_s": C * n * 100 / (ms * 1e-3),
+           "out_GB": C * n * 100 * 4 / 1e9}
+    del out, ws, x
+    plan.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_length_sweep(reps=100):
     """Length sweep (section "Wavelength and flexibility", Figure 4): signals of
     N = 100 ... 2500 samples at 1000 Hz (every 100, the largest prime at or
@@ -862,6 +899,8 @@ def main():
     if args.length_sweep:
         result["length_sweep"] = bench_length_sweep()
         progress("length sweep done")
+        result["long_recording"] = bench_long_recording()
+        progress("long recording done")
 
     if args.stream_seconds > 0:
         legs = [
