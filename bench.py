@@ -841,15 +841,17 @@ def main():
     for prec in ("split_f16", "split_bf16"):
         pp = cwt.Plan(N, cfg["sfreq"], cfg["freqs"], n_cycles=cfg["n_cycles"], out=args.out,
                       precision=prec)
+        # its own workspace: band power on these kernels also holds chunk rows
+        wsp = pp.alloc_workspace(C)
         with torch.cuda.stream(stream):
-            pp.forward_spectra(x, ws, stream=stream)
+            pp.forward_spectra(x, wsp, stream=stream)
             for i in range(3):
-                pp.transform_spectra(C, ring[i * ob:(i + 1) * ob], ws, stream=stream)
+                pp.transform_spectra(C, ring[i * ob:(i + 1) * ob], wsp, stream=stream)
             torch.cuda.synchronize()
             pp.timing_start(K)
             for i in range(K):
                 j = i % RING
-                pp.transform_spectra(C, ring[j * ob:(j + 1) * ob], ws, stream=stream)
+                pp.transform_spectra(C, ring[j * ob:(j + 1) * ob], wsp, stream=stream)
             ms_p = float(np.mean(pp.timing_stop()))
         run = {"precision": prec, "transform_ms": ms_p,
                "transform_pts_per_s": pts / (ms_p * 1e-3),
