@@ -199,9 +199,10 @@ typedef struct cwt_plan_desc {
     int32_t out;             /* enum cwt_out                                   */
     int32_t precision;       /* enum cwt_precision                             */
     int32_t wavelet;
-    int32_t threads;         /* threads per workgroup of the transform kernel  */
+    int32_t threads;         /* threads per workgroup of the transform kernel
+                                (the register-resident kernel's when kernel = 1) */
     int32_t n_passes;        /* radix passes                                    */
-    int32_t radix[16];       /* radix of each pass                              */
+    int32_t radix[16];       /* radix of each pass (of that kernel)             */
     int64_t out_rows;        /* rows per channel: n_freqs, or n_bands            */
     int64_t out_elem_bytes;  /* 8 (complex64) or 4 (float32)                     */
     int64_t spectrum_bins;   /* total stored wavelet-spectrum bins (all freqs)   */

@@ -15,7 +15,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libcwt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["cwt_api.cpp", "cwt_mem.cpp", "cwt_kernels.hip", "cwt_fixed.hip", "cwt_split.hip", "cwt_stream_kernels.hip",
+SOURCES = ["cwt_api.cpp", "cwt_mem.cpp", "cwt_kernels.hip", "cwt_fixed.hip", "cwt_mixed.hip", "cwt_split.hip", "cwt_stream_kernels.hip",
            "cwt_noalloc.hip", "cwt_pipeline.cpp", "cwt_user.cpp", "cwt_stream.cpp", "cwt_batch.cpp", "cwt_tune.cpp"]
 
 COMMON = [

@@ -550,7 +550,7 @@ int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
     // Register-resident kernels serve the lengths that have one, unless the
     // environment variable CWT_GENERIC_ONLY=1 asks for the generic kernel.
     const char *gen = std::getenv("CWT_GENERIC_ONLY");
-    P.use_fixed = fixed_main_available(P.L) && !(gen && gen[0] == '1') && P.n_seg == 0;
+    P.use_fixed = reg_main_available(P.L) && !(gen && gen[0] == '1') && P.n_seg == 0;
     set_chunks(P);
     const char *var = std::getenv("CWT_FIXED_VARIANT");
     P.variant = var ? std::atoi(var) : 1;
@@ -791,7 +791,7 @@ int enqueue_forward(const cwt_plan &P, const float *x, int64_t C, int64_t x_stri
     fp.Lh = P.L / 2 + 1;
     fp.tw = P.d_tw;
     fp.rp = P.rp;
-    hipError_t e = P.use_fixed ? launch_forward_fixed(fp, s) : launch_forward(fp, s);
+    hipError_t e = P.use_fixed ? launch_forward_reg(fp, s) : launch_forward(fp, s);
     if (e != hipSuccess) return hip_fail(e, "forward FFT launch");
     return CWT_OK;
 }
@@ -841,7 +841,7 @@ int enqueue_transform(const cwt_plan &P, int64_t C, void *out, void *ws, hipStre
         mp.grp_off = P.d_chunk;
     }
     const LaunchEvents ev = next_launch_events(P);
-    hipError_t e = (P.use_fixed) ? launch_main_fixed(mp, s, ev) : launch_main(mp, s, ev);
+    hipError_t e = (P.use_fixed) ? launch_main_reg(mp, s, ev) : launch_main(mp, s, ev);
     if (e != hipSuccess) return hip_fail(e, "transform launch");
     if (part) return enqueue_chunk_reduce(P, C, part, out, s);
     return CWT_OK;
@@ -901,6 +901,16 @@ static void fill_desc(const cwt_plan *P, cwt_plan_desc *d)
     d->threads = P->rp.threads;
     d->n_passes = P->rp.n_pass;
     for (int i = 0; i < P->rp.n_pass && i < 16; ++i) d->radix[i] = P->rp.radix[i];
+    if (P->use_fixed && P->opts.precision == CWT_PREC_FP32) {
+        // the register-resident kernel's own schedule
+        int r[16], th = 0;
+        const int n = reg_schedule(P->L, P->opts.out == CWT_OUT_BANDPOWER_F32, r, &th);
+        if (n > 0) {
+            d->threads = th;
+            d->n_passes = n;
+            for (int i = 0; i < 16; ++i) d->radix[i] = (i < n) ? r[i] : 0;
+        }
+    }
     d->out_rows = (P->opts.out == CWT_OUT_BANDPOWER_F32) ? P->n_bands : P->F;
     d->out_elem_bytes = (P->opts.out == CWT_OUT_COMPLEX64) ? 8 : 4;
     d->spectrum_bins = P->total_bins;
@@ -975,7 +985,7 @@ int check_exec_args(const cwt_plan *P, const float *x, bool x_needed, int64_t C,
     // one workgroup per output row; a launch holds fewer than 2^32 work-items
     // (the forward-FFT workgroups of a pipelined launch included)
     const int64_t threads = (P->opts.precision != CWT_PREC_FP32) ? 256
-                            : P->use_fixed                       ? P->L / 16
+                            : P->use_fixed                       ? reg_row_threads(P->L)
                                                                  : P->rp.threads;
     const int64_t fwd_blocks = (C * (P->n_seg ? P->n_seg : 1) + 1) / 2;
     if ((C * rows + fwd_blocks) * threads >= ((int64_t)1 << 32))

@@ -8,6 +8,7 @@
 
 #include "../../include/cwt.h"
 #include "cwt_kernels.hpp"
+#include "cwt_mixed.hpp"
 
 struct cwt_split_state;  // split-precision (MFMA) tables, when built
 

@@ -2,7 +2,7 @@
 //
 // Plans with a register-resident transform kernel run one launch per batch
 // on the caller's stream: the transform of batch i and the forward FFT of
-// batch i + 1 share the launch (launch_fused_fixed), the forward writing the
+// batch i + 1 share the launch (launch_fused_reg), the forward writing the
 // other half of a double-buffered workspace.  Stream order alone separates
 // a half's writer from its reader, so there are no events and no second
 // stream.  Other plans run forward then transform per batch.
@@ -101,7 +101,7 @@ extern "C" int cwt_execute_batches(const cwt_plan *P, const float *x, int64_t x_
         const MainParams mp = transform_params(*P, C, ob(i), ws_half[i & 1]);
         if (i + 1 < n_batches) {
             const FwdParams fp = forward_params(*P, xb(i + 1), C, ws_half[(i + 1) & 1]);
-            hipError_t e = launch_fused_fixed(mp, fp, s, next_launch_events(*P));
+            hipError_t e = launch_fused_reg(mp, fp, s, next_launch_events(*P));
             if (e != hipSuccess) return hip_fail(e, "fused transform + forward launch");
         } else {
             rc = enqueue_transform(*P, C, ob(i), ws_half[i & 1], s);

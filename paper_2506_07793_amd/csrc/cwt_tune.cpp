@@ -99,7 +99,7 @@ void apply_tuning_cache(cwt_plan &P)
             if ((S + threads - 1) / threads > std::max(1, maxv / rp.radix[i])) ok = 0;
         }
         if (!ok) continue;
-        if (kernel == 1 && !fixed_main_available(L)) continue;
+        if (kernel == 1 && !reg_main_available(L)) continue;
         best = Config{kernel == 1, variant, rp};
         found = true;  // the last matching line wins
     }
@@ -156,7 +156,7 @@ extern "C" int cwt_plan_autotune(cwt_plan *P, int64_t C, void *stream, cwt_tune_
     std::vector<Config> cands;
     const Config orig{P->use_fixed, P->variant, P->rp};
     cands.push_back(orig);
-    if (fixed_main_available(P->L)) {
+    if (reg_main_available(P->L)) {
         cands.push_back(Config{true, 0, P->rp});
         cands.push_back(Config{true, 1, P->rp});
     }
@@ -197,7 +197,7 @@ extern "C" int cwt_plan_autotune(cwt_plan *P, int64_t C, void *stream, cwt_tune_
         res->n_candidates = (int)cands.size();
         res->kernel = b.use_fixed ? 1 : 0;
         res->variant = b.variant;
-        res->threads = b.use_fixed ? P->L / 16 : b.rp.threads;
+        res->threads = b.use_fixed ? reg_row_threads(P->L) : b.rp.threads;
         res->n_passes = b.rp.n_pass;
         for (int i = 0; i < b.rp.n_pass && i < 16; ++i) res->radix[i] = b.rp.radix[i];
         res->best_ms = best_ms;

@@ -115,26 +115,47 @@ def _fewest_feasible_passes(L):
 
 @pytest.mark.parametrize("L", [4116, 2187, 1680, 105, 98, 3072, 1000, 2000, 10000, 4096, 19440,
                                20000, 16800, 18375, 12288, 7203])
-def test_planner_takes_fewest_passes(L):
-    """The schedule has the fewest passes any feasible schedule of the
-    implemented radices has (brute force here), largest radix first, and
-    fits the workgroup and register budget."""
+def test_planner_takes_fewest_passes(L, monkeypatch):
+    """The runtime-radix schedule has the fewest passes any feasible schedule
+    of the implemented radices has (brute force here), largest radix first,
+    and fits the workgroup and register budget."""
+    monkeypatch.setenv("CWT_GENERIC_ONLY", "1")
     d = cwt.describe(L, 1000.0, np.array([10.0, 20.0]), n_cycles=7.0, pad="explicit",
                      explicit_len=L)
     radix = [d.radix[i] for i in range(d.n_passes)]
-    assert int(np.prod(radix)) == L
+    assert d.kernel == 0 and int(np.prod(radix)) == L
     assert radix == sorted(radix, reverse=True)
-    if d.kernel == 0:  # the runtime-radix kernel's schedule
-        assert d.n_passes == _fewest_feasible_passes(L), radix
+    assert d.n_passes == _fewest_feasible_passes(L), radix
+
+
+@pytest.mark.parametrize("L,out,kernel,radix,threads", [
+    (1000, "complex64", 1, [5, 20, 10], 250), (1000, "bandpower", 1, [5, 20, 10], 250),
+    (2000, "power", 1, [5, 20, 20], 300), (4096, "complex64", 1, [16, 16, 16], 256),
+    (4096, "bandpower", 1, [16, 16, 16], 1024), (8192, "bandpower", 1, [16, 16, 16, 2], 1024),
+    (1200, "complex64", 0, None, None), (1024, "power", 1, [16, 16, 4], 64)])
+def test_register_kernel_schedule(L, out, kernel, radix, threads):
+    """Lengths with a register-resident kernel (powers of two 1024-8192, and
+    the mixed-radix 1000 = 5*20*10, 2000 = 5*20*20 with 20 values per thread
+    and 5 or 3 transforms per workgroup) select it and describe its own
+    passes and workgroup; others take the runtime-radix kernel."""
+    freqs = synth.log_freqs(1.0, 100.0, 20)
+    d = cwt.describe(L, 1000.0, freqs, n_cycles=synth.eeg_cycles(freqs), pad="explicit",
+                     explicit_len=L, out=out)
+    assert d.kernel == kernel
+    if kernel == 1:
+        assert [d.radix[i] for i in range(d.n_passes)] == radix and d.threads == threads
+        assert all(20 % r == 0 for r in radix) or L in (1024, 2048, 4096, 8192)
 
 
 @pytest.mark.parametrize("L,radix", [
     (1000, [10, 10, 10]), (2000, [20, 20, 5]), (4116, [21, 14, 14]), (2187, [9, 9, 9, 3]),
     (105, [15, 7]), (98, [14, 7]), (4096, [16, 16, 16]),
 ])
-def test_composite_radices_save_passes(L, radix):
-    """Small factors share a pass: 1000 = 10 x 10 x 10 (three passes instead
-    of 8 x 5 x 5 x 5), 2000 = 20 x 20 x 5, 4116 = 21 x 14 x 14."""
+def test_composite_radices_save_passes(L, radix, monkeypatch):
+    """Runtime-radix schedules: small factors share a pass: 1000 = 10 x 10 x
+    10 (three passes instead of 8 x 5 x 5 x 5), 2000 = 20 x 20 x 5, 4116 =
+    21 x 14 x 14."""
+    monkeypatch.setenv("CWT_GENERIC_ONLY", "1")
     d = cwt.describe(L, 1000.0, np.array([10.0, 20.0]), n_cycles=7.0, pad="explicit",
                      explicit_len=L)
     assert [d.radix[i] for i in range(d.n_passes)] == radix
@@ -498,15 +519,17 @@ def test_struct_layouts_match_the_header(tmp_path):
 
 
 @pytest.mark.parametrize("n,F,prec,expect_chunks", [(4096, 100, "fp32", False),
-                                                     (2000, 100, "fp32", True),
+                                                     (2000, 100, "fp32", False),
+                                                     (1200, 100, "fp32", True),
                                                      (4096, 100, "split_f16", True),
-                                                     (2000, 40, "fp32", True),
+                                                     (1200, 40, "fp32", True),
                                                      (3000, 5, "fp32", False)])
 def test_band_chunks(n, F, prec, expect_chunks):
     """Band power on the runtime-radix and split-precision kernels cuts each
     band into chunks of at most ceil(largest band / 4) frequencies (sizes
-    within one of each other); the register-resident FP32 kernel keeps one
-    row per band, and so does a grid whose bands are all single frequencies."""
+    within one of each other); the register-resident FP32 kernels (powers of
+    two, and the mixed-radix L = 1000 and 2000) keep one row per band, and so
+    does a grid whose bands are all single frequencies."""
     import oracle
     # five frequencies: one in each EEG band
     freqs = np.array([2.0, 6.0, 10.0, 20.0, 50.0]) if F == 5 else synth.log_freqs(1.0, 100.0, F)

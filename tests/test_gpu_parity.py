@@ -411,19 +411,21 @@ def test_band_path_edges(L, out):
 
 @pytest.mark.parametrize("n,precision,out", [(4096, "fp32", "complex64"), (4096, "fp32", "bandpower"),
                                              (1000, "fp32", "power"), (4096, "split_bf16", "complex64"),
-                                             (1000, "fp32", "complex64")])
+                                             (1000, "fp32", "complex64"), (2000, "fp32", "bandpower"),
+                                             (1200, "fp32", "power"), (1200, "fp32", "complex64")])
 def test_execute_batches_matches_execute(n, precision, out):
     """cwt_execute_batches gives, batch for batch, exactly cwt_execute's
-    output: with the register-resident kernel (L = 4096, transform of one
-    batch and forward FFT of the next in one launch), with the runtime-radix
-    kernel (L = 1000) and with the split-precision path; a zero stride reuses
-    one buffer; n_batches = 0 is a no-op; bad arguments are rejected."""
+    output: with the register-resident kernels (L = 4096 and the mixed-radix
+    L = 1000 and 2000; transform of one batch and forward FFT of the next in
+    one launch), with the runtime-radix kernel (L = 1200) and with the
+    split-precision path; a zero stride reuses one buffer; n_batches = 0 is a
+    no-op; bad arguments are rejected."""
     C, nb = 3, 5
     d = synth.eeg_64ch(C=C * nb, N=n, F=40)
     x = torch.from_numpy(d["x"]).cuda().view(nb, C, -1)
     plan = cwt.Plan(n, d["sfreq"], d["freqs"], n_cycles=d["n_cycles"], precision=precision,
                     out=out)
-    assert plan.desc.kernel == (1 if n == 4096 else 0)
+    assert plan.desc.kernel == (1 if n in (1000, 2000, 4096) else 0)
     refs = [plan.execute(x[i]).clone() for i in range(nb)]
     outb = torch.stack([torch.empty_like(refs[0]) for _ in range(nb)])
     ws = plan.alloc_batches_workspace(C)
@@ -656,7 +658,7 @@ def _skipped_passes(K, L, radices):
 
 @pytest.mark.parametrize("L", [98, 1000, 1680, 2187, 4116, 10000])
 @pytest.mark.parametrize("out", ["complex64", "power", "bandpower"])
-def test_generic_band_prologue(L, out):
+def test_generic_band_prologue(L, out, monkeypatch):
     """Runtime-radix kernel: rows whose band fits in L / Ns consecutive bins
     replace the first passes (radix product Ns) by one complex product per
     element.  The grid mixes 3-, 12- and 80-cycle wavelets from 0.3 Hz to
@@ -670,7 +672,9 @@ def test_generic_band_prologue(L, out):
     cyc = np.concatenate([np.tile([3.0, 12.0, 80.0], 8), [3.0, 2000.0, 1000.0]])
     rng = np.random.default_rng(L + 7)
     x = rng.normal(0, 20, size=(2, N)).astype(np.float32)
+    monkeypatch.setenv("CWT_GENERIC_ONLY", "1")  # L = 1000 has a register-resident kernel
     plan, W = _run(x, sfreq, freqs, cyc, pad="explicit", explicit_len=L, out=out)
+    monkeypatch.delenv("CWT_GENERIC_ONLY")
     assert plan.L == L and plan.desc.kernel == 0
     rad = plan.radices
     _, band, _ = plan.tables()
@@ -703,11 +707,13 @@ def test_generic_band_prologue(L, out):
     plan.close()
 
 
-@pytest.mark.parametrize("L", [1000, 4116, 4096, 2048])
-def test_generic_band_prologue_sampled_wavelets(L):
+@pytest.mark.parametrize("L,generic", [(1000, True), (4116, True), (4096, False), (2048, False),
+                                       (1000, False), (2000, False)])
+def test_generic_band_prologue_sampled_wavelets(L, generic, monkeypatch):
     """Narrow bands with complex spectra (plans from sampled wavelets): the
-    runtime-radix prologue (L 1000, 4116) and the register-resident band path
-    (L 4096, 2048).  A float32 wavelet's rounding noise reaches every bin, so
+    runtime-radix prologue (L 1000, 4116), the register-resident band path
+    (L 4096, 2048) and the mixed-radix register-resident first-pass
+    prologue (L 1000, 2000).  A float32 wavelet's rounding noise reaches every bin, so
     only wavelets with exactly representable single-bin spectra have narrow
     bands: i^j (bin L/4) and (-1)^j (bin L/2), one bin each, beside two
     Gaussian-windowed tones whose bands cover the spectrum."""
@@ -720,8 +726,11 @@ def test_generic_band_prologue_sampled_wavelets(L):
                    np.exp(-0.5 * (t / 0.02) ** 2) * np.exp(2j * np.pi * 90.0 * t)]) / 50.0
     freqs = np.array([250.0, 499.0, 30.0, 90.0])
     x = synth.eeg(2, N, sfreq, 11)
+    if generic:
+        monkeypatch.setenv("CWT_GENERIC_ONLY", "1")
     plan = cwt.Plan.from_wavelets(N, sfreq, freqs, wv, pad="explicit", explicit_len=L)
-    fixed = L in (2048, 4096)
+    monkeypatch.delenv("CWT_GENERIC_ONLY", raising=False)
+    fixed = not generic
     assert plan.L == L and plan.desc.kernel == (1 if fixed else 0)
     assert plan.desc.spectrum_complex == 1
     _, band, _ = plan.tables()
@@ -756,3 +765,77 @@ def test_launch_work_item_limit():
     plan.forward_spectra(x[:1000], ws)  # 1000 x 4096 x 1024 < 2^32
     torch.cuda.synchronize()
     plan.close()
+
+
+@pytest.mark.parametrize("L", [1000, 2000])
+@pytest.mark.parametrize("out", ["complex64", "power", "bandpower"])
+def test_mixed_radix_register_kernel(L, out, monkeypatch):
+    """Mixed-radix register-resident kernels (L = 1000 = 5*10*20, 2000 =
+    5*20*20; 20 values per thread, 5 or 3 transforms per workgroup): rows
+    whose band fits in S = L / 5 bins replace the first pass by one product
+    per element, wider rows stage their band and run every pass.  The grid
+    mixes both kinds (and bands wrapping past bin 0), 5 channels (a forward
+    pair past the last channel), a row count that is not a multiple of the
+    transforms per workgroup and a ragged crop; every row against the oracle,
+    and the whole output against the runtime-radix kernel's."""
+    sfreq = 1000.0
+    N = L - 7
+    S = L // 5
+    freqs = np.concatenate([synth.log_freqs(0.4, 470.0, 20), [499.0, 12.0, 60.0]])
+    cyc = np.concatenate([np.tile([3.0, 7.0, 40.0, 9.0], 5), [3.0, 300.0, 2.5]])
+    C = 5
+    x = synth.eeg(C, N, sfreq, L + 3)
+    plan, W = _run(x, sfreq, freqs, cyc, pad="explicit", explicit_len=L, out=out)
+    assert plan.L == L and plan.desc.kernel == 1
+    _, band, _ = plan.tables()
+    narrow = band[:, 1] <= S
+    print("L=%d: %d narrow rows (K <= %d), %d wide; K = %s" % (
+        L, narrow.sum(), S, (~narrow).sum(), band[:, 1].tolist()))
+    assert narrow.any() and (~narrow).any()
+    assert (band[narrow, 0] < 0).any(), "no wrapped band among the narrow rows"
+    ref = oracle.cwt(x.astype(np.float64), sfreq, freqs, cyc, L=L)
+    if out == "complex64":
+        pw = np.abs(ref) ** 2
+        for i in range(len(freqs)):
+            if pw[:, i].max() < 1e-6 * pw.max():
+                continue
+            e_P, _ = oracle.parity_errors(W[:, i], ref[:, i])
+            assert e_P <= TOL_P, (i, bool(narrow[i]), e_P)
+        _parity(W, ref, "mixed radix L=%d" % L)
+    else:
+        Pr = oracle.power(ref)
+        if out == "bandpower":
+            Pr = oracle.band_power(Pr, oracle.band_groups(freqs))
+        e = np.max(np.abs(W - Pr)) / Pr.max()
+        print("mixed radix L=%d %s e=%.3e" % (L, out, e))
+        assert e <= TOL_P
+    monkeypatch.setenv("CWT_GENERIC_ONLY", "1")
+    gplan, Wg = _run(x, sfreq, freqs, cyc, pad="explicit", explicit_len=L, out=out)
+    monkeypatch.delenv("CWT_GENERIC_ONLY")
+    assert gplan.desc.kernel == 0
+    scale = np.abs(Wg).max()
+    d = np.abs(W - Wg).max() / scale
+    print("  against the runtime-radix kernel: max |diff| / max = %.2e" % d)
+    assert d <= 2e-6
+    plan.close()
+    gplan.close()
+
+
+@pytest.mark.parametrize("L,variant", [(1000, 0), (2000, 0), (1000, 1)])
+def test_mixed_radix_twiddle_variants_and_sizes(L, variant, monkeypatch):
+    """Both twiddle methods of the mixed-radix kernels (table, powers), one
+    channel (the forward's second channel absent) and 64 channels (many
+    workgroups; the last partly filled), against the oracle on sampled rows."""
+    monkeypatch.setenv("CWT_FIXED_VARIANT", str(variant))
+    d = synth.eeg_64ch(C=64, N=L, F=37)
+    for C in (1, 64):
+        x = d["x"][:C]
+        plan, W = _run(x, d["sfreq"], d["freqs"], d["n_cycles"])
+        assert plan.L == L and plan.desc.kernel == 1
+        rows = np.array([(c, f) for c in sorted({0, C // 2, C - 1}) for f in (0, 11, 23, 36)])
+        ref = oracle.cwt(x.astype(np.float64), d["sfreq"], d["freqs"], d["n_cycles"], rows=rows)
+        got = np.stack([W[c, f] for c, f in rows])
+        e_P, e_W = oracle.parity_errors(got, ref)
+        print("L=%d variant %d C=%d: e_P=%.3e e_W=%.3e" % (L, variant, C, e_P, e_W))
+        assert e_P <= TOL_P
+        plan.close()
