@@ -235,6 +235,33 @@ def test_stages_equal_execute():
     plan.close()
 
 
+def test_paper_workload_20480_sampled():
+    """The paper's own throughput workload at its full size (64 channels x 10 s
+    at 2048 Hz = 20 480 samples, the largest padded length one workgroup
+    transforms; Morlet sigma 7 at 30-90 Hz in 1 Hz steps), as the bench
+    times it: sampled rows against the oracle over windows at both ends and
+    the middle (each output a full cyclic sum over L)."""
+    C, n, sfreq = 64, 20480, 2048.0
+    freqs = np.arange(30.0, 91.0)
+    x = synth.eeg(C, n, sfreq, 46)
+    plan, W = _run(x, sfreq, freqs, 7.0)
+    assert plan.L == 20480 and plan.n_segments == 0
+    rng = np.random.default_rng(47)
+    rows = [(int(c), int(f)) for c, f in zip(rng.integers(0, C, 8), rng.integers(0, 61, 8))]
+    got, ref = [], []
+    for t0 in (0, n // 2 - 32, n - 64):
+        ref.append(oracle.cwt(x.astype(np.float64), sfreq, freqs, 7.0, rows=rows, t0=t0, nt=64))
+        got.append(np.stack([W[c, f, t0:t0 + 64] for c, f in rows]))
+    got, ref = np.concatenate(got, axis=1), np.concatenate(ref, axis=1)
+    # scale each row by its largest power over the whole row (the library's)
+    for r, (c, f) in enumerate(rows):
+        scale = float((np.abs(W[c, f]) ** 2).max())
+        e = float(np.abs(np.abs(got[r]) ** 2 - np.abs(ref[r]) ** 2).max() / scale)
+        assert e <= TOL_P, (c, f, e)
+    _parity(got, ref, "paper workload L=20480 radices=%s" % plan.radices)
+    plan.close()
+
+
 def test_max_length_20000_sampled():
     """Largest supported padded length (160 KB of LDS), oracle on sampled rows."""
     x = synth.eeg(2, 20000, 2048.0, seed=3)
