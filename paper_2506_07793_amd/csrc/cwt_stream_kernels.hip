@@ -61,11 +61,20 @@ hipError_t launch_stream_gather(const StreamParams &p, hipStream_t s)
 }
 
 // One workgroup per (window-channel row, grouped frequency): the band
-// products X~[b] H_f[b] of the frequency are staged in LDS and read by every
-// lane; lane t handles trailing samples t, t + T, ... < hop, with the
-// twiddles exp(2 pi i b t / L) read from the table, the index advanced
-// exactly in integers.  The lanes' sums of |W_f[t]|^2 are reduced in a fixed
-// order and written to part[row][q].
+// products y[k] = X~[b] H_f[b], b = lo + k, of the frequency are staged in
+// LDS and read by every lane; lane t handles trailing samples t, t + T, ...
+// < hop.  With s = exp(2 pi i t_a / L) (t_a the sample's index in the
+// window), W_f[t_a] = sum over chunks of G bins of
+//   exp(2 pi i (lo + k0) t_a / L) * sum_{j < G} y[k0 + j] s^j,
+// the inner sum by Horner's rule (one complex multiply-add per bin, no
+// table read) and the chunk's root read from the table at an index advanced
+// exactly in integers; the rounding of the at most G - 1 products by s stays
+// within a few units of the last place of each chunk sum.  (Reading every
+// root from the table, one gather per bin, made the kernel bound by those
+// gathers: 4.5x slower at L = 5600.)  The lanes' sums of |W_f[t]|^2 are
+// reduced in a fixed order and written to part[row][q].
+constexpr int kHornerChunk = 8;
+
 __global__ void __launch_bounds__(128) k_stream_freqpower(StreamBPParams p)
 {
     extern __shared__ cf ys[];
@@ -91,16 +100,28 @@ __global__ void __launch_bounds__(128) k_stream_freqpower(StreamBPParams p)
     __syncthreads();
     float psum = 0.f;
     for (int t = tid; t < p.hop; t += T) {
-        const int ta = t0 + t;
-        int idx = (int)(((int64_t)lo_u * ta) % L);
+        const int ta = t0 + t;  // < W <= L
+        const cf sr = tw[ta];   // exp(2 pi i t_a / L)
+        const int step = (int)(((int64_t)kHornerChunk * ta) % L);
+        int idx = (int)(((int64_t)lo_u * ta) % L);  // root index of the chunk's first bin
         float ar = 0.f, ai = 0.f;
-        for (int k = 0; k < K; ++k) {
-            const cf y = ys[k];
+        int k0 = 0;
+        for (; k0 + kHornerChunk <= K; k0 += kHornerChunk) {
+            cf c = ys[k0 + kHornerChunk - 1];
+#pragma unroll
+            for (int j = kHornerChunk - 2; j >= 0; --j) c = add(mul(c, sr), ys[k0 + j]);
             const cf w = tw[idx];
-            ar += y.x * w.x - y.y * w.y;
-            ai += y.x * w.y + y.y * w.x;
-            idx += ta;
+            ar += c.x * w.x - c.y * w.y;
+            ai += c.x * w.y + c.y * w.x;
+            idx += step;
             if (idx >= L) idx -= L;
+        }
+        if (k0 < K) {  // the last, partial chunk
+            cf c = ys[K - 1];
+            for (int j = K - 2; j >= k0; --j) c = add(mul(c, sr), ys[j]);
+            const cf w = tw[idx];
+            ar += c.x * w.x - c.y * w.y;
+            ai += c.x * w.y + c.y * w.x;
         }
         psum += ar * ar + ai * ai;
     }
