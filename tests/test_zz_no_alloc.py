@@ -38,7 +38,8 @@ def _noalloc(lib, plan, x, out):
 CASES = [
     # (label, n, sfreq, n_freqs, out mode, precision, C first, C second)
     ("register-resident L=4096 complex64", 4096, 1000.0, 100, "complex64", "fp32", 64, 5),
-    ("runtime radices L=2000 power", 2000, 1000.0, 40, "power", "fp32", 24, 3),
+    ("mixed-radix register-resident L=2000 power", 2000, 1000.0, 40, "power", "fp32", 24, 3),
+    ("runtime radices L=3000 power", 3000, 1000.0, 40, "power", "fp32", 24, 3),
     ("band power L=4096", 4096, 1000.0, 40, "bandpower", "fp32", 16, 1),
     ("split FP16 L=4096 complex64", 4096, 1000.0, 30, "complex64", "split_f16", 8, 2),
 ]
