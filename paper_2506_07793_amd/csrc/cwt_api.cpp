@@ -88,7 +88,7 @@ static bool composite_radix(int r)
 }
 
 // Fewest factors reachable from f by merging pairs into composite radices of
-// at most maxv whose pass still fits a 1024-thread workgroup (L / R
+// at most maxv whose pass still fits the class's largest workgroup (L / R
 // butterflies, maxv / R per thread); exhaustive over the few factors a
 // length has.
 static void merge_factors(std::vector<int> &f, int maxv, int L)
@@ -97,7 +97,8 @@ static void merge_factors(std::vector<int> &f, int maxv, int L)
     for (size_t i = 0; i < f.size(); ++i)
         for (size_t j = i + 1; j < f.size(); ++j) {
             const int pr = f[i] * f[j];
-            if (!composite_radix(pr) || pr > maxv || L / pr > 1024 * (maxv / pr)) continue;
+            if (!composite_radix(pr) || pr > maxv || L / pr > generic_max_threads(maxv) * (maxv / pr))
+                continue;
             std::vector<int> g;
             for (size_t k = 0; k < f.size(); ++k)
                 if (k != i && k != j) g.push_back(f[k]);
@@ -114,8 +115,8 @@ static void merge_factors(std::vector<int> &f, int maxv, int L)
 // factors are paired into composite radices (2x3, 3x3, 2x5, 4x3, 2x7, 3x5)
 // wherever that saves passes, and the passes run largest radix first.  The
 // workgroup size is the smallest multiple of 64 (at least L/16) for which no
-// thread holds more than maxv values in any pass; maxv is 16 when possible,
-// else 24.
+// thread holds more than maxv values in any pass (maxv: the class asked for,
+// 16, 24 or 32, with its own largest workgroup).
 static bool try_radix_plan(int L, const int *order, int n_order, int maxv, bool merge,
                            RadixPlan &rp)
 {
@@ -140,7 +141,8 @@ static bool try_radix_plan(int L, const int *order, int n_order, int maxv, bool 
     for (int r : f) rp.radix[np++] = r;
     if (np == 0) rp.radix[np++] = 1;  // L == 1: a single identity pass
     rp.n_pass = np;
-    for (int T = std::max(64, std::min(1024, ((L / 16 + 63) / 64) * 64)); T <= 1024; T += 64) {
+    const int tmax = generic_max_threads(maxv);
+    for (int T = std::max(64, std::min(tmax, ((L / 16 + 63) / 64) * 64)); T <= tmax; T += 64) {
         bool ok = true;
         for (int i = 0; i < np && ok; ++i) {
             const int R = rp.radix[i];
@@ -175,9 +177,9 @@ void radix_candidates(int L, std::vector<RadixPlan> &out)
         for (int mul = 1; mul <= 2; ++mul) {
             RadixPlan c = ranked[i];
             c.threads = ranked[i].threads * mul;
-            if (c.threads <= 1024) out.push_back(c);
+            if (c.threads <= generic_max_threads(c.maxv)) out.push_back(c);
         }
-    for (int maxv : {16, 24})
+    for (int maxv : {16, 24, 32})
         for (bool merge : {true, false})
             for (int o = 0; o < 3; ++o) {
                 RadixPlan rp;
@@ -185,7 +187,7 @@ void radix_candidates(int L, std::vector<RadixPlan> &out)
                 for (int mul = 1; mul <= 2; ++mul) {
                     RadixPlan c = rp;
                     c.threads = rp.threads * mul;
-                    if (c.threads > 1024) continue;
+                    if (c.threads > generic_max_threads(maxv)) continue;
                     bool dup = false;
                     for (const RadixPlan &q : out)
                         if (q.threads == c.threads && q.maxv == c.maxv && q.n_pass == c.n_pass &&
@@ -201,17 +203,18 @@ static const int kRadices[] = {24, 21, 20, 16, 15, 14, 12, 10, 9, 8, 7, 6, 5, 4,
 
 // Workgroup size for a schedule at maxv values per thread: the smallest
 // multiple of 64 (at least L/16) for which every pass's butterflies fit, or
-// 0 when none up to 1024 does.
+// 0 when none up to the class's largest workgroup does.
 static int schedule_threads(int L, const std::vector<int> &f, int maxv)
 {
-    int need = std::max(64, std::min(1024, ((L / 16 + 63) / 64) * 64));
+    const int tmax = generic_max_threads(maxv);
+    int need = std::max(64, std::min(tmax, ((L / 16 + 63) / 64) * 64));
     for (int R : f) {
         if (R > maxv) return 0;
         const int mb = std::max(1, maxv / R);
         const int t = (L / R + mb - 1) / mb;
         need = std::max(need, ((t + 63) / 64) * 64);
     }
-    return need <= 1024 ? need : 0;
+    return need <= tmax ? need : 0;
 }
 
 // All schedules (radix multisets, largest radix first) whose product is L.
@@ -233,8 +236,10 @@ static void enum_schedules(int rem, int maxr, std::vector<int> &cur,
 
 // Feasible plans of length L ordered best first: fewest passes (each pass is
 // one LDS round trip and two barriers, and its twiddle products), then the
-// least lane work Σ T ceil((L/R)/T) R (idle lanes of partly filled
-// butterfly rounds count), then fewer values per thread.
+// 16- and 24-value classes before the 32-value one (which runs at most 12
+// waves per workgroup, with more registers each), then the least lane work
+// Σ T ceil((L/R)/T) R (idle lanes of partly filled butterfly rounds count),
+// then fewer values per thread.
 static void ranked_plans(int L, std::vector<RadixPlan> &out)
 {
     out.clear();
@@ -247,7 +252,7 @@ static void ranked_plans(int L, std::vector<RadixPlan> &out)
     };
     std::vector<Cand> c;
     for (const auto &f : scheds)
-        for (int maxv : {16, 24}) {
+        for (int maxv : {16, 24, 32}) {
             const int T = schedule_threads(L, f, maxv);
             if (!T) continue;
             RadixPlan rp{};
@@ -262,6 +267,7 @@ static void ranked_plans(int L, std::vector<RadixPlan> &out)
         }
     std::stable_sort(c.begin(), c.end(), [](const Cand &a, const Cand &b) {
         if (a.rp.n_pass != b.rp.n_pass) return a.rp.n_pass < b.rp.n_pass;
+        if ((a.rp.maxv > 24) != (b.rp.maxv > 24)) return b.rp.maxv > 24;
         if (a.work != b.work) return a.work < b.work;
         return a.rp.maxv < b.rp.maxv;
     });
@@ -515,7 +521,18 @@ int validate_and_plan(cwt_plan &P, int64_t n, double sfreq, const double *freqs,
                         CWT_MAX_LEN, (long long)S, (long long)Lmax);
         const int64_t nseg = (n + (Lmax - 2 * S) - 1) / (Lmax - 2 * S);
         const int64_t B = (n + nseg - 1) / nseg;
-        const int64_t Ls = pad_length(B + 2 * S, CWT_PAD_SMOOTH7, 0);
+        // The segment transform: the smallest 7-smooth length holding B + 2S,
+        // or 16384 / 20480 when one of those holds it with at most 10% more
+        // points: their schedules are radix-16 passes (16·16·16·4, 16·16·16·5),
+        // which cost about 2.8 ns per output point at 64 channels x 100
+        // frequencies against 3.3-4.8 for the other 7-smooth lengths from
+        // 19 600 to 20 412 (20 160 = 24·21·20·2: 4.75).
+        int64_t Ls = pad_length(B + 2 * S, CWT_PAD_SMOOTH7, 0);
+        for (const int64_t fast : {(int64_t)16384, Lmax})
+            if (fast >= B + 2 * S && 10 * fast <= 11 * Ls) {
+                Ls = fast;
+                break;
+            }
         P.n_seg = (int)nseg;
         P.seg_B = (int)B;
         P.seg_S = (int)S;

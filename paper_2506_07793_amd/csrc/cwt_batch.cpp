@@ -37,11 +37,15 @@ size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // Workgroup-size classes: a task may run with more threads than its plan
 // needs (each thread then holds fewer butterflies), never fewer.
-int class_threads(int t)
+// Workgroup size of a class: the plan's rounded up to 64, 128, 256, 512 or
+// the largest workgroup of its values-per-thread class (1024, or 768 for 32
+// values per thread, whose kernels are compiled for at most 768 threads).
+int class_threads(int t, int maxv)
 {
-    for (int c : {64, 128, 256, 512, 1024})
+    const int tmax = generic_max_threads(maxv);
+    for (int c : {64, 128, 256, 512})
         if (t <= c) return c;
-    return 1024;
+    return tmax;
 }
 
 struct ClassInfo {
@@ -331,7 +335,7 @@ extern "C" int cwt_execute_batch(const cwt_batch_item *items, int32_t n, void *w
     for (int i = 0; i < n && persistent; ++i) {
         const cwt_plan &P = *items[i].plan;
         if (items[i].C == 0) continue;
-        const int thr = class_threads(P.rp.threads);
+        const int thr = class_threads(P.rp.threads, P.rp.maxv);
         const bool one_row = P.rp.maxv > 16;
         ClassInfo &c = by_class[{thr, P.rp.maxv, one_row ? (int)P.opts.out : -1}];
         c.threads = thr;

@@ -10,6 +10,13 @@
 #include "cwt_kernels.hpp"
 #include "cwt_mixed.hpp"
 
+namespace cwtk {
+// Most threads per workgroup of a runtime-radix plan holding at most maxv
+// values per thread in a pass (the kernels' launch bound of that class:
+// 1024 for 16 and 24 values, 768 for 32).
+inline int generic_max_threads(int maxv) { return maxv > 24 ? 768 : 1024; }
+}  // namespace cwtk
+
 struct cwt_split_state;  // split-precision (MFMA) tables, when built
 
 namespace cwtrt {

@@ -9,6 +9,8 @@
 //                multiply over the stored band of the wavelet spectrum ->
 //                LDS-resident inverse Stockham FFT -> crop to n samples ->
 //                complex64 / |W|^2 / band-mean store, natural order.
+#include <type_traits>
+
 #include "cwt_kernels.hpp"
 #include "fft_core.hpp"
 
@@ -111,6 +113,26 @@ hipError_t launch_user_spectra(const float2 *w, int F, int wl, int c, int L, dou
 // --------------------------------------------------------- forward FFT --
 
 // Forward transform of channel pair `pair` (channels 2 pair, 2 pair + 1).
+// Most threads per workgroup of a runtime-radix kernel class, by the most
+// values a thread holds in a pass: 1024 for the 16- and 24-value classes,
+// 768 for the 32-value one, which at 12 waves per workgroup may use up to
+// 168 registers per lane (the 24-value class, held to 128 by its 1024-thread
+// bound, spills a few).
+template <int MAXV>
+struct GenThreads {
+    static constexpr int value = MAXV > 24 ? 768 : 1024;
+};
+
+// Calls f with the compiled values-per-thread class of a plan (16, 24 or 32)
+// as a compile-time constant.
+template <class F>
+static hipError_t with_maxv(int maxv, F &&f)
+{
+    if (maxv <= 16) return f(std::integral_constant<int, 16>{});
+    if (maxv <= 24) return f(std::integral_constant<int, 24>{});
+    return f(std::integral_constant<int, 32>{});
+}
+
 template <int MAXV, class P = FwdParams>
 __device__ __forceinline__ void forward_task(const P &p, int pair)
 {
@@ -167,7 +189,7 @@ __device__ __forceinline__ void forward_task(const P &p, int pair)
 }
 
 template <int MAXV>
-__global__ void __launch_bounds__(1024) k_forward(FwdParams p)
+__global__ void __launch_bounds__(GenThreads<MAXV>::value) k_forward(FwdParams p)
 {
     forward_task<MAXV>(p, blockIdx.x);
 }
@@ -181,14 +203,14 @@ hipError_t launch_forward(const FwdParams &p, hipStream_t s)
 {
     const int blocks = (p.C + 1) / 2;
     const size_t lds = generic_lds_bytes(p.rp.L);
-    if (p.rp.maxv <= 16) {
-        set_lds_limit((const void *)k_forward<16>, lds);
-        hipLaunchKernelGGL(k_forward<16>, dim3(blocks), dim3(p.rp.threads), lds, s, p);
-    } else {
-        set_lds_limit((const void *)k_forward<24>, lds);
-        hipLaunchKernelGGL(k_forward<24>, dim3(blocks), dim3(p.rp.threads), lds, s, p);
-    }
-    return hipGetLastError();
+    return with_maxv(p.rp.maxv, [&](auto mv) {
+        constexpr int M = decltype(mv)::value;
+        // the kernels of a class are compiled for at most its workgroup size
+        if (p.rp.threads > GenThreads<M>::value) return hipErrorInvalidConfiguration;
+        set_lds_limit((const void *)k_forward<M>, lds);
+        hipLaunchKernelGGL(k_forward<M>, dim3(blocks), dim3(p.rp.threads), lds, s, p);
+        return hipGetLastError();
+    });
 }
 
 // --------------------------------------------------------- main kernel --
@@ -453,7 +475,7 @@ __device__ __forceinline__ void main_task(const P &p, int c, int row)
 }
 
 template <int MAXV, int MODE>
-__global__ void __launch_bounds__(1024) k_main(MainParams p)
+__global__ void __launch_bounds__(GenThreads<MAXV>::value) k_main(MainParams p)
 {
     const int c = blockIdx.x / p.n_rows;
     const int row = blockIdx.x - c * p.n_rows;
@@ -476,7 +498,7 @@ __device__ __forceinline__ int claim_task(int *counter)
 }
 
 template <int MAXV>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(GenThreads<MAXV>::value)
     k_batch_forward(const FwdParams *items, const BatchTask *tasks, int n, int *counter)
 {
     for (;;) {
@@ -489,7 +511,7 @@ __global__ void __launch_bounds__(1024)
 }
 
 template <int MAXV>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(GenThreads<MAXV>::value)
     k_batch_main(const MainParams *items, const BatchTask *tasks, int n, int *counter)
 {
     for (;;) {
@@ -515,7 +537,7 @@ __global__ void __launch_bounds__(1024)
 // read through the constant address space, so that its fields may be loaded
 // again after each out-of-line pass instead of being held in registers.
 template <int MAXV, int MODE>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(GenThreads<MAXV>::value)
     k_batch_rows(const MainParams *items, const BatchTask *rows)
 {
     typedef const __attribute__((address_space(4))) MainParams CMP;
@@ -530,7 +552,7 @@ __global__ void __launch_bounds__(1024)
 // constant address space: a captured graph of these launches stays valid for
 // any later call with the same layout, as the table is uploaded per call.
 template <int MAXV>
-__global__ void __launch_bounds__(1024) k_item_forward(const FwdParams *items, int item)
+__global__ void __launch_bounds__(GenThreads<MAXV>::value) k_item_forward(const FwdParams *items, int item)
 {
     typedef const __attribute__((address_space(4))) FwdParams CFP;
     CFP &p = *(CFP *)(items + item);
@@ -538,7 +560,7 @@ __global__ void __launch_bounds__(1024) k_item_forward(const FwdParams *items, i
 }
 
 template <int MAXV, int MODE>
-__global__ void __launch_bounds__(1024) k_item_main(const MainParams *items, int item)
+__global__ void __launch_bounds__(GenThreads<MAXV>::value) k_item_main(const MainParams *items, int item)
 {
     typedef const __attribute__((address_space(4))) MainParams CMP;
     CMP &p = *(CMP *)(items + item);
@@ -575,36 +597,32 @@ hipError_t launch_batch_forward(const FwdParams *items, const BatchTask *tasks, 
                                 int *counter, int threads, int maxv, size_t lds, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    if (maxv <= 16) {
-        set_lds_limit((const void *)k_batch_forward<16>, lds);
-        const int g = occupancy_grid(k_batch_forward<16>, threads, lds, n);
-        hipLaunchKernelGGL(k_batch_forward<16>, dim3(g), dim3(threads), lds, s, items, tasks, n,
+    return with_maxv(maxv, [&](auto mv) {
+        constexpr int M = decltype(mv)::value;
+        // the kernels of a class are compiled for at most its workgroup size
+        if (threads > GenThreads<M>::value) return hipErrorInvalidConfiguration;
+        set_lds_limit((const void *)k_batch_forward<M>, lds);
+        const int g = occupancy_grid(k_batch_forward<M>, threads, lds, n);
+        hipLaunchKernelGGL(k_batch_forward<M>, dim3(g), dim3(threads), lds, s, items, tasks, n,
                            counter);
-    } else {
-        set_lds_limit((const void *)k_batch_forward<24>, lds);
-        const int g = occupancy_grid(k_batch_forward<24>, threads, lds, n);
-        hipLaunchKernelGGL(k_batch_forward<24>, dim3(g), dim3(threads), lds, s, items, tasks, n,
-                           counter);
-    }
-    return hipGetLastError();
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_batch_main(const MainParams *items, const BatchTask *tasks, int n,
                              int *counter, int threads, int maxv, size_t lds, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    if (maxv <= 16) {
-        set_lds_limit((const void *)k_batch_main<16>, lds);
-        const int g = occupancy_grid(k_batch_main<16>, threads, lds, n);
-        hipLaunchKernelGGL(k_batch_main<16>, dim3(g), dim3(threads), lds, s, items, tasks, n,
+    return with_maxv(maxv, [&](auto mv) {
+        constexpr int M = decltype(mv)::value;
+        // the kernels of a class are compiled for at most its workgroup size
+        if (threads > GenThreads<M>::value) return hipErrorInvalidConfiguration;
+        set_lds_limit((const void *)k_batch_main<M>, lds);
+        const int g = occupancy_grid(k_batch_main<M>, threads, lds, n);
+        hipLaunchKernelGGL(k_batch_main<M>, dim3(g), dim3(threads), lds, s, items, tasks, n,
                            counter);
-    } else {
-        set_lds_limit((const void *)k_batch_main<24>, lds);
-        const int g = occupancy_grid(k_batch_main<24>, threads, lds, n);
-        hipLaunchKernelGGL(k_batch_main<24>, dim3(g), dim3(threads), lds, s, items, tasks, n,
-                           counter);
-    }
-    return hipGetLastError();
+        return hipGetLastError();
+    });
 }
 
 template <int MAXV, int MODE>
@@ -628,32 +646,30 @@ hipError_t launch_batch_rows(const MainParams *items, const BatchTask *rows, int
                              int maxv, int mode, size_t lds, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    if (maxv <= 16) {
+    return with_maxv(maxv, [&](auto mv) {
+        constexpr int M = decltype(mv)::value;
+        // the kernels of a class are compiled for at most its workgroup size
+        if (threads > GenThreads<M>::value) return hipErrorInvalidConfiguration;
         switch (mode) {
-        case kOutComplex: return launch_batch_rows_t<16, kOutComplex>(items, rows, n, threads, lds, s);
-        case kOutPower: return launch_batch_rows_t<16, kOutPower>(items, rows, n, threads, lds, s);
-        default: return launch_batch_rows_t<16, kOutBand>(items, rows, n, threads, lds, s);
+        case kOutComplex: return launch_batch_rows_t<M, kOutComplex>(items, rows, n, threads, lds, s);
+        case kOutPower: return launch_batch_rows_t<M, kOutPower>(items, rows, n, threads, lds, s);
+        default: return launch_batch_rows_t<M, kOutBand>(items, rows, n, threads, lds, s);
         }
-    }
-    switch (mode) {
-    case kOutComplex: return launch_batch_rows_t<24, kOutComplex>(items, rows, n, threads, lds, s);
-    case kOutPower: return launch_batch_rows_t<24, kOutPower>(items, rows, n, threads, lds, s);
-    default: return launch_batch_rows_t<24, kOutBand>(items, rows, n, threads, lds, s);
-    }
+    });
 }
 
 hipError_t launch_item_forward(const FwdParams *items, int item, int blocks, int threads,
                                int maxv, size_t lds, hipStream_t s)
 {
     if (blocks == 0) return hipSuccess;
-    if (maxv <= 16) {
-        set_lds_limit((const void *)k_item_forward<16>, lds);
-        hipLaunchKernelGGL(k_item_forward<16>, dim3(blocks), dim3(threads), lds, s, items, item);
-    } else {
-        set_lds_limit((const void *)k_item_forward<24>, lds);
-        hipLaunchKernelGGL(k_item_forward<24>, dim3(blocks), dim3(threads), lds, s, items, item);
-    }
-    return hipGetLastError();
+    return with_maxv(maxv, [&](auto mv) {
+        constexpr int M = decltype(mv)::value;
+        // the kernels of a class are compiled for at most its workgroup size
+        if (threads > GenThreads<M>::value) return hipErrorInvalidConfiguration;
+        set_lds_limit((const void *)k_item_forward<M>, lds);
+        hipLaunchKernelGGL(k_item_forward<M>, dim3(blocks), dim3(threads), lds, s, items, item);
+        return hipGetLastError();
+    });
 }
 
 template <int MAXV, int MODE>
@@ -670,18 +686,16 @@ hipError_t launch_item_main(const MainParams *items, int item, int blocks, int t
                             int mode, size_t lds, hipStream_t s)
 {
     if (blocks == 0) return hipSuccess;
-    if (maxv <= 16) {
+    return with_maxv(maxv, [&](auto mv) {
+        constexpr int M = decltype(mv)::value;
+        // the kernels of a class are compiled for at most its workgroup size
+        if (threads > GenThreads<M>::value) return hipErrorInvalidConfiguration;
         switch (mode) {
-        case kOutComplex: return launch_item_main_t<16, kOutComplex>(items, item, blocks, threads, lds, s);
-        case kOutPower: return launch_item_main_t<16, kOutPower>(items, item, blocks, threads, lds, s);
-        default: return launch_item_main_t<16, kOutBand>(items, item, blocks, threads, lds, s);
+        case kOutComplex: return launch_item_main_t<M, kOutComplex>(items, item, blocks, threads, lds, s);
+        case kOutPower: return launch_item_main_t<M, kOutPower>(items, item, blocks, threads, lds, s);
+        default: return launch_item_main_t<M, kOutBand>(items, item, blocks, threads, lds, s);
         }
-    }
-    switch (mode) {
-    case kOutComplex: return launch_item_main_t<24, kOutComplex>(items, item, blocks, threads, lds, s);
-    case kOutPower: return launch_item_main_t<24, kOutPower>(items, item, blocks, threads, lds, s);
-    default: return launch_item_main_t<24, kOutBand>(items, item, blocks, threads, lds, s);
-    }
+    });
 }
 
 template <int MAXV, int MODE>
@@ -752,18 +766,16 @@ hipError_t launch_chunk_reduce(const ChunkReduceParams &p, hipStream_t s)
 
 hipError_t launch_main(const MainParams &p, hipStream_t s, LaunchEvents ev)
 {
-    if (p.rp.maxv <= 16) {
+    return with_maxv(p.rp.maxv, [&](auto mv) {
+        constexpr int M = decltype(mv)::value;
+        // the kernels of a class are compiled for at most its workgroup size
+        if (p.rp.threads > GenThreads<M>::value) return hipErrorInvalidConfiguration;
         switch (p.out_mode) {
-        case kOutComplex: return launch_main_t<16, kOutComplex>(p, s, ev);
-        case kOutPower: return launch_main_t<16, kOutPower>(p, s, ev);
-        default: return launch_main_t<16, kOutBand>(p, s, ev);
+        case kOutComplex: return launch_main_t<M, kOutComplex>(p, s, ev);
+        case kOutPower: return launch_main_t<M, kOutPower>(p, s, ev);
+        default: return launch_main_t<M, kOutBand>(p, s, ev);
         }
-    }
-    switch (p.out_mode) {
-    case kOutComplex: return launch_main_t<24, kOutComplex>(p, s, ev);
-    case kOutPower: return launch_main_t<24, kOutPower>(p, s, ev);
-    default: return launch_main_t<24, kOutBand>(p, s, ev);
-    }
+    });
 }
 
 }  // namespace cwtk

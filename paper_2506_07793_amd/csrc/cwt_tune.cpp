@@ -91,7 +91,8 @@ void apply_tuning_cache(cwt_plan &P)
             rp.radix[i] = r;
             prod *= r;
         }
-        if (!ok || prod != L || threads < 64 || threads > 1024 || (maxv != 16 && maxv != 24))
+        if (!ok || prod != L || threads < 64 || (maxv != 16 && maxv != 24 && maxv != 32) ||
+            threads > generic_max_threads(maxv))
             continue;
         // every pass's butterflies fit the workgroup (as the planner requires)
         for (int i = 0; i < n && ok; ++i) {

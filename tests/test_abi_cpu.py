@@ -72,9 +72,11 @@ def test_padded_length_and_radices(n, pad, expl, L):
     # composites 2x3, 3x3, 2x5, 4x3, 2x7, 3x5 (and 4x5, 3x7, 8x3 in plans of
     # 24 values per thread) that merge small factors
     assert all(r in RADICES for r in radix)
-    # no thread holds more values than the kernel's register budget
-    maxv = 16 if all(-(-(L // r) // d.threads) <= max(1, 16 // r) and r <= 16
-                     for r in radix) else 24
+    # no thread holds more values than the kernel's register budget (the
+    # smallest class the schedule fits; 32 values only at <= 768 threads)
+    maxv = next(m for m in (16, 24, 32)
+                if all(-(-(L // r) // d.threads) <= max(1, m // r) and r <= m for r in radix))
+    assert maxv < 32 or d.threads <= 768
     for r in radix:
         nb = -(-(L // r) // d.threads)
         assert nb <= max(1, maxv // r)
@@ -86,17 +88,17 @@ RADICES = (1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 14, 15, 16, 20, 21, 24)
 
 def _fewest_feasible_passes(L):
     """Brute force: the fewest passes of any schedule of implemented radices
-    whose product is L and whose butterflies fit one workgroup of at most
-    1024 threads holding at most 16 (or 24) values each (radices above 16
-    only at 24), with at least L/16 threads."""
+    whose product is L and whose butterflies fit one workgroup holding at
+    most 16 or 24 values per thread (at most 1024 threads; radices above 16
+    only at 24) or 32 (at most 768 threads), with at least L/16 threads."""
     best = None
-    for maxv in (16, 24):
+    for maxv, tmax in ((16, 1024), (24, 1024), (32, 768)):
         rad = [r for r in RADICES if 1 < r <= maxv]
-        t_min = max(64, min(1024, -(-(L // 16) // 64) * 64))
+        t_min = max(64, min(tmax, -(-(L // 16) // 64) * 64))
 
         def fits(r):
             mb = max(1, maxv // r)
-            return -(-(-(-(L // r) // mb)) // 64) * 64 <= 1024 and t_min <= 1024
+            return -(-(-(-(L // r) // mb)) // 64) * 64 <= tmax and t_min <= tmax
 
         ok = [r for r in rad if fits(r)]
         memo = {}
@@ -370,6 +372,13 @@ def test_segmented_plan_geometry(n, pad, sfreq, fmin):
     B, Ls = d.segment_outputs, d.segment_len
     assert (d.n_segments - 1) * B < n <= d.n_segments * B
     assert B + 2 * S <= Ls <= 20480 and _smooth7(Ls)
+    # the smallest 7-smooth length holding B + 2S, or 16384 / 20480 (radix-16
+    # schedules) when one holds it with at most 10% more points
+    m = B + 2 * S
+    while not _smooth7(m):
+        m += 1
+    want = next((f for f in (16384, 20480) if m <= f and 10 * f <= 11 * m), m)
+    assert Ls == want, (Ls, want, m)
     assert d.kernel == 0  # the runtime-radix kernel runs the segments
 
 

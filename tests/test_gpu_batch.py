@@ -54,7 +54,9 @@ def _check_item(it, got, rows, label):
 SPECS = [(1000, 3, 20, 250.0, "complex64"), (4116, 2, 33, 1000.0, "power"),
          (777, 5, 40, 500.0, "complex64"), (2048, 1, 25, 2048.0, "bandpower"),
          (12000, 2, 21, 1000.0, "power"), (105, 4, 24, 250.0, "complex64"),
-         (19999, 1, 20, 2048.0, "complex64")]
+         (19999, 1, 20, 2048.0, "complex64"),
+         # plans of the 32-value class (at most 768 threads): L = 19440 and 20412
+         (19440, 3, 16, 1000.0, "power"), (20400, 2, 12, 2048.0, "complex64")]
 
 
 @pytest.mark.parametrize("kernels", ["items", "persistent"])
@@ -63,6 +65,9 @@ def test_heterogeneous_batch_matches_oracle(graph, kernels, monkeypatch):
     monkeypatch.setenv("CWT_BATCH_GRAPH", graph)
     monkeypatch.setenv("CWT_BATCH_KERNELS", kernels)
     its = _items(SPECS, seed=30)
+    # the 32-value items run at most 768 threads per workgroup, also as a
+    # persistent class
+    assert sum(1 for it in its if it["plan"].desc.threads == 768 and it["plan"].L > 16384) == 2
     b = cwt.Batch([(it["plan"], it["xt"], it["out"]) for it in its])
     ws = b.alloc_workspace()
     b.execute(ws)

@@ -866,3 +866,44 @@ def test_mixed_radix_twiddle_variants_and_sizes(L, variant, monkeypatch):
         print("L=%d variant %d C=%d: e_P=%.3e e_W=%.3e" % (L, variant, C, e_P, e_W))
         assert e_P <= TOL_P
         plan.close()
+
+
+@pytest.mark.parametrize("L,radix", [(19683, [9, 9, 9, 9, 3]), (19440, [16, 15, 9, 9]),
+                                     (20480, [16, 16, 16, 5]), (16875, [15, 15, 15, 5]),
+                                     (14406, [21, 14, 7, 7])])
+@pytest.mark.parametrize("out", ["complex64", "bandpower"])
+def test_runtime_radix_32_value_plans(L, radix, out):
+    """Runtime-radix plans of the 32-value class (at most 768 threads, up to
+    32 values per thread in a pass), which the planner takes where they save
+    a pass (19683: 5 passes instead of 9; 19440: 4 instead of 6): sampled
+    rows over windows at both ends and the middle of a ragged crop against
+    the oracle, complex and band power."""
+    sfreq = 1000.0
+    N = L - 3
+    C = 3
+    freqs = synth.log_freqs(1.0, 100.0, 20)
+    cyc = synth.eeg_cycles(freqs)
+    x = synth.eeg(C, N, sfreq, L % 1000 + 5)
+    plan, W = _run(x, sfreq, freqs, cyc, pad="explicit", explicit_len=L, out=out)
+    assert plan.L == L and plan.desc.kernel == 0
+    assert plan.radices == radix and plan.desc.threads <= 768, (plan.radices, plan.desc.threads)
+    starts = (0, N // 2 - 32, N - 64)
+    x64 = x.astype(np.float64)
+    if out == "complex64":
+        rows = [(c, f) for c in range(C) for f in (0, 9, 19)]
+        ref = np.concatenate([oracle.cwt(x64, sfreq, freqs, cyc, L=L, rows=rows, t0=t0, nt=64)
+                              for t0 in starts], axis=1)
+        got = np.concatenate([np.stack([W[c, f, t0:t0 + 64] for c, f in rows]) for t0 in starts],
+                             axis=1)
+        _parity(got, ref, "32-value plan L=%d %s" % (L, radix))
+    else:
+        groups = oracle.band_groups(freqs)
+        rows = [(c, f) for c in range(C) for f in range(len(freqs))]
+        for t0 in (starts[0], starts[2]):
+            ref = oracle.cwt(x64, sfreq, freqs, cyc, L=L, rows=rows, t0=t0, nt=64)
+            P = (np.abs(ref) ** 2).reshape(C, len(freqs), 64)
+            Br = oracle.band_power(P, groups)
+            e = float(np.abs(W[:, :, t0:t0 + 64] - Br).max() / Br.max())
+            print("32-value plan L=%d band power window %d: e=%.3e" % (L, t0, e))
+            assert e <= TOL_P
+    plan.close()
