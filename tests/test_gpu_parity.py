@@ -870,14 +870,16 @@ def test_mixed_radix_twiddle_variants_and_sizes(L, variant, monkeypatch):
 
 @pytest.mark.parametrize("L,radix", [(19683, [9, 9, 9, 9, 3]), (19440, [16, 15, 9, 9]),
                                      (20480, [16, 16, 16, 5]), (16875, [15, 15, 15, 5]),
-                                     (14406, [21, 14, 7, 7])])
+                                     (14406, [21, 14, 7, 7]), (18432, [24, 24, 8, 4]),
+                                     (16800, [24, 14, 10, 5])])
 @pytest.mark.parametrize("out", ["complex64", "bandpower"])
 def test_runtime_radix_32_value_plans(L, radix, out):
     """Runtime-radix plans of the 32-value class (at most 768 threads, up to
     32 values per thread in a pass), which the planner takes where they save
-    a pass (19683: 5 passes instead of 9; 19440: 4 instead of 6): sampled
-    rows over windows at both ends and the middle of a ragged crop against
-    the oracle, complex and band power."""
+    a pass (19683: 5 passes instead of 9; 19440: 4 instead of 6) and, above
+    16 384 points, before the 24-value class at equal passes (18432, 16800):
+    sampled rows over windows at both ends and the middle of a ragged crop
+    against the oracle, complex and band power."""
     sfreq = 1000.0
     N = L - 3
     C = 3
