@@ -112,7 +112,6 @@ hipError_t launch_user_spectra(const float2 *w, int F, int wl, int c, int L, dou
 
 // --------------------------------------------------------- forward FFT --
 
-// Forward transform of channel pair `pair` (channels 2 pair, 2 pair + 1).
 // Most threads per workgroup of a runtime-radix kernel class, by the most
 // values a thread holds in a pass: 1024 for the 16- and 24-value classes,
 // 768 for the 32-value one, which at 12 waves per workgroup may use up to
@@ -133,6 +132,7 @@ static hipError_t with_maxv(int maxv, F &&f)
     return f(std::integral_constant<int, 32>{});
 }
 
+// Forward transform of channel pair `pair` (channels 2 pair, 2 pair + 1).
 template <int MAXV, class P = FwdParams>
 __device__ __forceinline__ void forward_task(const P &p, int pair)
 {
