@@ -240,7 +240,7 @@ int cwt_plan_describe(cwt_plan_desc *desc, int64_t n, double sfreq, const double
 
 /*
  * Autotuner.  Times the candidate kernel configurations of this plan on the
- * current device (generic kernel: the planner's four best-ranked schedules
+ * current device (generic kernel: the planner's eight best-ranked schedules
  * and the radix orders 16-first / 8-first / 4-first, 16 or 24 values per
  * thread in workgroups of up to 1024 threads or 32 in workgroups of up to
  * 768, minimal or doubled workgroup; for the lengths with a
