@@ -241,9 +241,13 @@ static void enum_schedules(int rem, int maxr, std::vector<int> &cur,
 // class first (at equal passes its schedules, radix-16 pairs without register
 // spills, ran 17-35% faster: 64 ch x 100 freqs, power, L = 16 800 524 -> 339
 // us, 18 432 475 -> 338, 19 200 492 -> 361, 20 160 533 -> 404), at or below
-// it the 16- and 24-value classes before the 32-value one; then the least
-// lane work Σ T ceil((L/R)/T) R (idle lanes of partly filled butterfly
-// rounds count), then fewer values per thread.
+// it the 16- and 24-value classes before the 32-value one; above 16 384,
+// then fewer passes of the three-factor composite radices 20, 21 and 24,
+// whose passes cost more per point than their lane work shows (defaults
+// 4-10% faster at 7 of 15 lengths tried, e.g. 18 432 [24, 24, 8, 4] 406 ->
+// [16, 12, 12, 8] 365 us, none slower by more than 1%); then the least lane
+// work Σ T ceil((L/R)/T) R (idle lanes of partly filled butterfly rounds
+// count), then fewer values per thread.
 static void ranked_plans(int L, std::vector<RadixPlan> &out)
 {
     out.clear();
@@ -259,6 +263,13 @@ static void ranked_plans(int L, std::vector<RadixPlan> &out)
     // 16 384 points (where only it and the 24-value class fit), else the
     // 16- and 24-value classes
     auto class_rank = [L](int maxv) { return (maxv > 24) == (L > 16384) ? 0 : 1; };
+    // passes of a composite radix with three prime factors (20, 21, 24)
+    auto triple_radices = [](const RadixPlan &rp) {
+        int n = 0;
+        for (int i = 0; i < rp.n_pass; ++i)
+            n += (rp.radix[i] == 20 || rp.radix[i] == 21 || rp.radix[i] == 24);
+        return n;
+    };
     for (const auto &f : scheds)
         for (int maxv : {16, 24, 32}) {
             const int T = schedule_threads(L, f, maxv);
@@ -273,10 +284,13 @@ static void ranked_plans(int L, std::vector<RadixPlan> &out)
             for (int R : f) work += (int64_t)T * ((L / R + T - 1) / T) * R;
             c.push_back({rp, work});
         }
-    std::stable_sort(c.begin(), c.end(), [&class_rank](const Cand &a, const Cand &b) {
+    std::stable_sort(c.begin(), c.end(), [&class_rank, &triple_radices, L](const Cand &a,
+                                                                           const Cand &b) {
         if (a.rp.n_pass != b.rp.n_pass) return a.rp.n_pass < b.rp.n_pass;
         if (class_rank(a.rp.maxv) != class_rank(b.rp.maxv))
             return class_rank(a.rp.maxv) < class_rank(b.rp.maxv);
+        if (L > 16384 && triple_radices(a.rp) != triple_radices(b.rp))
+            return triple_radices(a.rp) < triple_radices(b.rp);
         if (a.work != b.work) return a.work < b.work;
         return a.rp.maxv < b.rp.maxv;
     });

@@ -132,13 +132,14 @@ def test_planner_takes_fewest_passes(L, monkeypatch):
 
 @pytest.mark.parametrize("L,radix,threads", [(19200, [16, 16, 15, 5], 768),
                                             (20160, [16, 14, 10, 9], 768),
-                                            (20000, [20, 20, 10, 5], 1024),
+                                            (20000, [20, 10, 10, 10], 1024),
                                             (16384, [16, 16, 16, 4], 1024)])
 def test_runtime_radix_class_preference(L, radix, threads, monkeypatch):
     """Above 16 384 points the 32-value class (at most 768 threads) comes
     before the 24-value one at equal passes (19200, 20160), fewer passes
-    still come first (20000: 4 passes at 24 values, 5 at 32), and at or
-    below 16 384 the 16-value class keeps its schedules."""
+    still come first (20000: 4 passes at 24 values, 5 at 32), then fewer
+    passes of the three-factor composites 20, 21, 24 (20000: one instead of
+    two), and at or below 16 384 the 16-value class keeps its schedules."""
     monkeypatch.setenv("CWT_GENERIC_ONLY", "1")
     d = cwt.describe(L, 1000.0, np.array([10.0, 20.0]), n_cycles=7.0, pad="explicit",
                      explicit_len=L)

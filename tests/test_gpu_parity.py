@@ -870,8 +870,8 @@ def test_mixed_radix_twiddle_variants_and_sizes(L, variant, monkeypatch):
 
 @pytest.mark.parametrize("L,radix", [(19683, [9, 9, 9, 9, 3]), (19440, [16, 15, 9, 9]),
                                      (20480, [16, 16, 16, 5]), (16875, [15, 15, 15, 5]),
-                                     (14406, [21, 14, 7, 7]), (18432, [24, 24, 8, 4]),
-                                     (16800, [24, 14, 10, 5])])
+                                     (14406, [21, 14, 7, 7]), (18432, [16, 12, 12, 8]),
+                                     (16800, [15, 14, 10, 8]), (17496, [24, 9, 9, 9])])
 @pytest.mark.parametrize("out", ["complex64", "bandpower"])
 def test_runtime_radix_32_value_plans(L, radix, out):
     """Runtime-radix plans of the 32-value class (at most 768 threads, up to
