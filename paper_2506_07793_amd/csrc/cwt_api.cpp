@@ -241,13 +241,19 @@ static void enum_schedules(int rem, int maxr, std::vector<int> &cur,
 // class first (at equal passes its schedules, radix-16 pairs without register
 // spills, ran 17-35% faster: 64 ch x 100 freqs, power, L = 16 800 524 -> 339
 // us, 18 432 475 -> 338, 19 200 492 -> 361, 20 160 533 -> 404), at or below
-// it the 16- and 24-value classes before the 32-value one; above 16 384,
-// then fewer passes of the three-factor composite radices 20, 21 and 24,
-// whose passes cost more per point than their lane work shows (defaults
-// 4-10% faster at 7 of 15 lengths tried, e.g. 18 432 [24, 24, 8, 4] 406 ->
-// [16, 12, 12, 8] 365 us, none slower by more than 1%); then the least lane
-// work Σ T ceil((L/R)/T) R (idle lanes of partly filled butterfly rounds
-// count), then fewer values per thread.
+// it the 16- and 24-value classes before the 32-value one; then the least
+// lane work Σ T ceil((L/R)/T) R (idle lanes of partly filled butterfly
+// rounds count), then fewer values per thread.  Finally, among the plans
+// tied with the first on passes, class and workgroup size, the one with the
+// fewest passes of the three-factor composite radices 20, 21 and 24 goes
+// first: those passes cost more per point than their lane work shows.
+// Measured (64 ch, runtime-radix kernel; 61 freqs complex64 up to 14 000, 100
+// freqs power above): 2400 [20, 15, 8] 40.1 -> [16, 15, 10] 35.3 us, 3072
+// [24, 16, 8] 54.5 -> [16, 16, 12] 42.1, 14 000 [20, 14, 10, 5] 255 ->
+// [14, 10, 10, 10] 219, 18 432 [24, 24, 8, 4] 406 -> [16, 12, 12, 8] 365, but
+// 3528 [21, 21, 8] 57.7 -> [21, 14, 12] 62.6; where the alternative needs a
+// larger workgroup it was no faster (1400: [14, 10, 10] at 192 threads 8%
+// slower than [20, 14, 5] at 128, against 7% faster at 128).
 static void ranked_plans(int L, std::vector<RadixPlan> &out)
 {
     out.clear();
@@ -284,16 +290,29 @@ static void ranked_plans(int L, std::vector<RadixPlan> &out)
             for (int R : f) work += (int64_t)T * ((L / R + T - 1) / T) * R;
             c.push_back({rp, work});
         }
-    std::stable_sort(c.begin(), c.end(), [&class_rank, &triple_radices, L](const Cand &a,
-                                                                           const Cand &b) {
+    std::stable_sort(c.begin(), c.end(), [&class_rank](const Cand &a, const Cand &b) {
         if (a.rp.n_pass != b.rp.n_pass) return a.rp.n_pass < b.rp.n_pass;
         if (class_rank(a.rp.maxv) != class_rank(b.rp.maxv))
             return class_rank(a.rp.maxv) < class_rank(b.rp.maxv);
-        if (L > 16384 && triple_radices(a.rp) != triple_radices(b.rp))
-            return triple_radices(a.rp) < triple_radices(b.rp);
         if (a.work != b.work) return a.work < b.work;
         return a.rp.maxv < b.rp.maxv;
     });
+    // Among the plans tied with the first on passes, class and workgroup
+    // size, the one with the fewest passes of the three-factor composites
+    // goes first (the order is otherwise kept).
+    if (!c.empty()) {
+        const RadixPlan &h = c[0].rp;
+        size_t best = 0;
+        for (size_t i = 1; i < c.size(); ++i) {
+            const RadixPlan &a = c[i].rp;
+            if (a.n_pass != h.n_pass || class_rank(a.maxv) != class_rank(h.maxv) ||
+                a.threads != h.threads)
+                continue;
+            if (triple_radices(a) < triple_radices(c[best].rp)) best = i;
+        }
+        std::rotate(c.begin(), c.begin() + (std::ptrdiff_t)best,
+                    c.begin() + (std::ptrdiff_t)best + 1);
+    }
     for (const Cand &x : c) out.push_back(x.rp);
 }
 

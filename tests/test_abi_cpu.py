@@ -167,13 +167,14 @@ def test_register_kernel_schedule(L, out, kernel, radix, threads):
 
 
 @pytest.mark.parametrize("L,radix", [
-    (1000, [10, 10, 10]), (2000, [20, 20, 5]), (4116, [21, 14, 14]), (2187, [9, 9, 9, 3]),
+    (1000, [10, 10, 10]), (2000, [20, 10, 10]), (4116, [21, 14, 14]), (2187, [9, 9, 9, 3]),
     (105, [15, 7]), (98, [14, 7]), (4096, [16, 16, 16]),
 ])
 def test_composite_radices_save_passes(L, radix, monkeypatch):
     """Runtime-radix schedules: small factors share a pass: 1000 = 10 x 10 x
-    10 (three passes instead of 8 x 5 x 5 x 5), 2000 = 20 x 20 x 5, 4116 =
-    21 x 14 x 14."""
+    10 (three passes instead of 8 x 5 x 5 x 5), 2000 = 20 x 10 x 10 (one
+    three-factor composite instead of the two of 20 x 20 x 5 at the same
+    workgroup size), 4116 = 21 x 14 x 14."""
     monkeypatch.setenv("CWT_GENERIC_ONLY", "1")
     d = cwt.describe(L, 1000.0, np.array([10.0, 20.0]), n_cycles=7.0, pad="explicit",
                      explicit_len=L)
