@@ -147,6 +147,27 @@ def test_runtime_radix_class_preference(L, radix, threads, monkeypatch):
     assert [d.radix[i] for i in range(d.n_passes)] == radix and d.threads == threads
 
 
+@pytest.mark.parametrize("L,radix,threads", [(3072, [16, 16, 12], 192),
+                                            (12800, [16, 16, 10, 5], 832),
+                                            (14000, [14, 10, 10, 10], 1024),
+                                            (2400, [16, 15, 10], 192),
+                                            (3528, [21, 14, 12], 256)])
+def test_fewest_three_factor_composites_among_ties(L, radix, threads, monkeypatch):
+    """Among the plans tied with the best one on passes, value class and
+    workgroup size, the one with the fewest passes of the three-factor
+    composites 20, 21 and 24 is taken: 3072 = 16 x 16 x 12 (none) rather
+    than 24 x 16 x 8, 12800 = 16 x 16 x 10 x 5 rather than 20 x 20 x 16 x 2,
+    14000 = 14 x 10 x 10 x 10 rather than 20 x 14 x 10 x 5, and 3528 keeps
+    one 21 where no plan of three passes has none."""
+    monkeypatch.setenv("CWT_GENERIC_ONLY", "1")
+    d = cwt.describe(L, 1000.0, np.array([10.0, 20.0]), n_cycles=7.0, pad="explicit",
+                     explicit_len=L)
+    rad = [d.radix[i] for i in range(d.n_passes)]
+    assert d.kernel == 0
+    assert rad == radix and d.threads == threads
+    assert int(np.prod(rad)) == L
+
+
 @pytest.mark.parametrize("L,out,kernel,radix,threads", [
     (1000, "complex64", 1, [5, 20, 10], 250), (1000, "bandpower", 1, [5, 20, 10], 250),
     (2000, "power", 1, [5, 20, 20], 300), (4096, "complex64", 1, [16, 16, 16], 256),
