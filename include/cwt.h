@@ -244,7 +244,8 @@ int cwt_plan_describe(cwt_plan_desc *desc, int64_t n, double sfreq, const double
  * and the radix orders 16-first / 8-first / 4-first, 16 or 24 values per
  * thread in workgroups of up to 1024 threads or 32 in workgroups of up to
  * 768, minimal or doubled workgroup; for the lengths with a
- * register-resident kernel (powers of two 1024-8192, 800, 1000, 1600, 2000) also that
+ * register-resident kernel (powers of two 1024-8192; 200, 400, 800, 1000,
+ * 1600, 2000) also that
  * kernel with table or power twiddles) on min(C, 16) channels of zeros,
  * keeps the fastest in the
  * plan, and, when the environment variable CWT_AUTOTUNE_CACHE names a file,

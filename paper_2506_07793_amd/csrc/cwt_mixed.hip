@@ -1,6 +1,6 @@
 // Register-resident FFT kernels for padded lengths that are not powers of two
-// (gfx950): L = 800 = 4 x 10 x 20, 1000 = 5 x 20 x 10, 1600 = 4 x 20 x 20 and
-// 2000 = 5 x 20 x 20.
+// (gfx950): L = 200 = 10 x 20, 400 = 20 x 20, 800 = 4 x 10 x 20,
+// 1000 = 5 x 20 x 10, 1600 = 4 x 20 x 20 and 2000 = 5 x 20 x 20.
 //
 // The scheme of the power-of-two kernels, generalised.  Every thread holds
 // V = 20 complex values in registers and every radix of the compile-time list
@@ -9,10 +9,11 @@
 // butterfly kb in v[kb + r V / R], and the strides and twiddle indexes of every
 // pass are compile-time constants.  Before a pass, v[m] is element t + T m of
 // its input; after the last, sample t + T m of the output (natural order).
-// Since T (40, 50, 80 or 100) is not a multiple of the 64-lane wave, a
-// workgroup runs SUB transforms side by side, one per group of T threads with
-// its own LDS slab: 8 x 40 threads at L = 800, 5 x 50 at 1000, 4 x 80 at 1600
-// and 3 x 100 at 2000 (5, 4, 5 and 5 waves).
+// Since T (10, 20, 40, 50, 80 or 100) is not a multiple of the 64-lane wave,
+// a workgroup runs SUB transforms side by side, one per group of T threads
+// with its own LDS slab: 32 x 10 threads at L = 200, 16 x 20 at 400, 8 x 40
+// at 800, 5 x 50 at 1000, 4 x 80 at 1600 and 3 x 100 at 2000 (5 waves, 4 at
+// L = 1000).
 //
 // Inverse kernel.  The wavelet spectrum of one frequency is non-zero only on
 // a band of K cyclically consecutive bins.  The first pass (radix R0, no
@@ -52,7 +53,12 @@ struct MList<> {
 // Transforms per workgroup.
 template <int L>
 struct MSub {
-    static constexpr int value = (L == 800) ? 8 : (L == 1000) ? 5 : (L == 1600) ? 4 : 3;
+    static constexpr int value = (L == 200)    ? 32
+                                 : (L == 400)  ? 16
+                                 : (L == 800)  ? 8
+                                 : (L == 1000) ? 5
+                                 : (L == 1600) ? 4
+                                               : 3;
 };
 
 // LDS slots.  The buffer after pass p holds element i at slot
@@ -67,7 +73,7 @@ struct MSub {
 // included): 2.5 and 2.2 conflict cycles per access summed over the two
 // buffers (ideal 2.0), against 3.7 and 2.9 for plain slots with radices
 // [5, 10, 20] and [5, 20, 20]; each slab stays within the LDS that keeps 4
-// (L = 1000) or 3 (L = 800, 1600, 2000) workgroups on a CU.  At L = 800 and
+// (L = 1000) or 3 (the other lengths) workgroups on a CU.  At L = 800 and
 // 1600 the first radix is 4 (its first pass is the one a band of at most
 // L / 4 bins skips, which covers the EEG bands there), whose stride-4 scatter
 // no gap with P a multiple of T spreads: 4.0 and 4.3 in the model against 4.8
@@ -81,6 +87,22 @@ struct MPad<1000, 0> {
 template <>
 struct MPad<1000, 1> {
     static constexpr int C = 1, P = 100;
+};
+template <>
+struct MPad<200, 0> {
+    static constexpr int C = 1, P = 30;
+};
+template <>
+struct MPad<200, 1> {  // two passes: one buffer
+    static constexpr int C = 1, P = 30;
+};
+template <>
+struct MPad<400, 0> {
+    static constexpr int C = 1, P = 80;
+};
+template <>
+struct MPad<400, 1> {  // two passes: one buffer
+    static constexpr int C = 1, P = 80;
 };
 template <>
 struct MPad<800, 0> {
@@ -470,8 +492,8 @@ struct MShape {
 
 // Waves per SIMD the register budget allows: four (at most 128 registers)
 // for complex and power rows with power twiddles, which with a workgroup's
-// LDS is 4 workgroups per CU at L = 1000 (16 waves) and 3 at L = 800, 1600
-// and 2000 (15);
+// LDS is 4 workgroups per CU at L = 1000 (16 waves) and 3 at the other
+// lengths (15);
 // three for band rows (20 running sums) and for table twiddles (their loads
 // are issued early), which would otherwise spill.
 template <int MODE, int TWM>
@@ -598,11 +620,16 @@ hipError_t launch_mixed_forward_t(const FwdParams &f, hipStream_t s)
 
 }  // namespace
 
-bool mixed_main_available(int L) { return L == 800 || L == 1000 || L == 1600 || L == 2000; }
+bool mixed_main_available(int L)
+{
+    return L == 200 || L == 400 || L == 800 || L == 1000 || L == 1600 || L == 2000;
+}
 
 int mixed_block_threads(int L)
 {
     switch (L) {
+    case 200: return MShape<10, 20>::threads;
+    case 400: return MShape<20, 20>::threads;
     case 800: return MShape<4, 10, 20>::threads;
     case 1000: return MShape<5, 20, 10>::threads;
     case 1600: return MShape<4, 20, 20>::threads;
@@ -616,7 +643,8 @@ int reg_schedule(int L, bool band, int *radix, int *threads)
     // power-of-two kernels: radix 16 first, L / 16 threads per transform, 4
     // (L <= 4096) or 2 transforms per workgroup in band-power mode
     static const int p1024[] = {16, 16, 4}, p2048[] = {16, 16, 8}, p4096[] = {16, 16, 16},
-                     p8192[] = {16, 16, 16, 2}, m800[] = {4, 10, 20}, m1000[] = {5, 20, 10},
+                     p8192[] = {16, 16, 16, 2}, m200[] = {10, 20}, m400[] = {20, 20},
+                     m800[] = {4, 10, 20}, m1000[] = {5, 20, 10},
                      m1600[] = {4, 20, 20}, m2000[] = {5, 20, 20};
     const int *r = nullptr;
     int n = 0;
@@ -625,6 +653,8 @@ int reg_schedule(int L, bool band, int *radix, int *threads)
     case 2048: r = p2048, n = 3, *threads = (band ? 4 : 1) * (L / 16); break;
     case 4096: r = p4096, n = 3, *threads = (band ? 4 : 1) * (L / 16); break;
     case 8192: r = p8192, n = 4, *threads = (band ? 2 : 1) * (L / 16); break;
+    case 200: r = m200, n = 2, *threads = MShape<10, 20>::threads; break;
+    case 400: r = m400, n = 2, *threads = MShape<20, 20>::threads; break;
     case 800: r = m800, n = 3, *threads = MShape<4, 10, 20>::threads; break;
     case 1000: r = m1000, n = 3, *threads = MShape<5, 20, 10>::threads; break;
     case 1600: r = m1600, n = 3, *threads = MShape<4, 20, 20>::threads; break;
@@ -639,6 +669,8 @@ hipError_t launch_main_mixed(const MainParams &p, hipStream_t s, LaunchEvents ev
 {
     if (p.C <= 0 || p.n_rows <= 0) return hipSuccess;
     switch (p.rp.L) {
+    case 200: return launch_mixed_main_v<10, 20>(p, s, ev);
+    case 400: return launch_mixed_main_v<20, 20>(p, s, ev);
     case 800: return launch_mixed_main_v<4, 10, 20>(p, s, ev);
     case 1000: return launch_mixed_main_v<5, 20, 10>(p, s, ev);
     case 1600: return launch_mixed_main_v<4, 20, 20>(p, s, ev);
@@ -651,6 +683,8 @@ hipError_t launch_forward_mixed(const FwdParams &f, hipStream_t s)
 {
     if (f.C <= 0) return hipSuccess;
     switch (f.rp.L) {
+    case 200: return launch_mixed_forward_t<10, 20>(f, s);
+    case 400: return launch_mixed_forward_t<20, 20>(f, s);
     case 800: return launch_mixed_forward_t<4, 10, 20>(f, s);
     case 1000: return launch_mixed_forward_t<5, 20, 10>(f, s);
     case 1600: return launch_mixed_forward_t<4, 20, 20>(f, s);
@@ -665,6 +699,8 @@ hipError_t launch_fused_mixed(const MainParams &p, const FwdParams &f, hipStream
     // both roles have work (a launch of the pipelined batches)
     if (p.C <= 0 || p.n_rows <= 0 || f.C <= 0) return hipErrorInvalidValue;
     switch (p.rp.L) {
+    case 200: return launch_mixed_fused_v<10, 20>(p, f, s, ev);
+    case 400: return launch_mixed_fused_v<20, 20>(p, f, s, ev);
     case 800: return launch_mixed_fused_v<4, 10, 20>(p, f, s, ev);
     case 1000: return launch_mixed_fused_v<5, 20, 10>(p, f, s, ev);
     case 1600: return launch_mixed_fused_v<4, 20, 20>(p, f, s, ev);
