@@ -150,7 +150,8 @@ def parse():
                     help="real-time length of each streaming run (0 skips the streaming runs; "
                          "60 gives the 60 s serving runs of the serving workload)")
     ap.add_argument("--length-sweep", type=int, default=1,
-                    help="1: run the N = 100..2500 length sweep (0 skips it)")
+                    help="1: run the N = 100..2500 length sweep, the long recording, the "
+                         "paper's workload and the epoch lengths (0 skips them)")
     ap.add_argument("--preroll-ms", type=float, default=300.0,
                     help="untimed pipelined steps before the warm-up until at least this much "
                          "GPU time has passed and two consecutive chunk means agree within 2%% "
@@ -429,6 +430,58 @@ def bench_length_sweep(reps=100):
                           "prime_over_neighbours_mean": float(np.mean(ratios))}
     res["plan_create_ms_N1000_61_wavelets"] = dict(t_create)[1000]
     return res
+
+
+def bench_epoch_lengths(reps=50):
+    """EEG epochs of 4, 5, 8 and 10 s at 1000 Hz (L = 4000, 5000, 8000, 10000):
+    64 channels, the 100-frequency EEG grid (1-100 Hz, n_cycles = f / 2 in
+    [3, 10]), complex64 out; `reps` cwt_execute calls per length, timed with
+    events, with the default plan (the mixed-radix register-resident kernel)
+    and with CWT_GENERIC_ONLY=1 (the runtime-radix kernel)."""
+    import os
+
+    import torch
+
+    import paper_2506_07793_amd as cwt
+    import synth
+
+    sfreq = 1000.0
+    freqs = synth.log_freqs(1.0, 100.0, 100)
+    cyc = synth.eeg_cycles(freqs)
+    stream = torch.cuda.Stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rows = []
+    for N in (4000, 5000, 8000, 10000):
+        x = torch.from_numpy(synth.eeg(64, N, sfreq, 17)).cuda()
+        rec = {"N": N}
+        for label, generic in (("register", False), ("runtime_radix", True)):
+            prev = os.environ.pop("CWT_GENERIC_ONLY", None)
+            if generic:
+                os.environ["CWT_GENERIC_ONLY"] = "1"
+            try:
+                plan = cwt.Plan(N, sfreq, freqs, n_cycles=cyc, stream=stream)
+            finally:
+                os.environ.pop("CWT_GENERIC_ONLY", None)
+                if prev is not None:
+                    os.environ["CWT_GENERIC_ONLY"] = prev
+            out = plan.alloc_output(64)
+            ws = plan.alloc_workspace(64)
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                for _ in range(5):
+                    plan.execute(x, out=out, ws=ws, stream=stream)
+                ev0.record(stream)
+                for _ in range(reps):
+                    plan.execute(x, out=out, ws=ws, stream=stream)
+                ev1.record(stream)
+                torch.cuda.synchronize()
+            rec[label] = {"L": plan.L, "kernel": int(plan.desc.kernel), "radices": plan.radices,
+                          "ms": ev0.elapsed_time(ev1) / reps}
+            del out, ws
+            plan.close()
+        rows.append(rec)
+    return {"workload": "64 ch x N at 1000 Hz, 100 log freqs 1-100 Hz, complex64, %d calls "
+                        "per length and kernel" % reps, "lengths": rows}
 
 
 def bench_stream(n_sessions, C, sfreq, win_s, hop_s, seconds, seed, max_batch, deadline_us,
@@ -958,6 +1011,8 @@ def main():
         progress("long recording done")
         result["paper_workload"] = bench_paper_workload()
         progress("paper's workload done")
+        result["epoch_lengths"] = bench_epoch_lengths()
+        progress("epoch lengths done")
 
     if args.stream_seconds > 0:
         legs = [
