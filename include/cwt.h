@@ -245,7 +245,7 @@ int cwt_plan_describe(cwt_plan_desc *desc, int64_t n, double sfreq, const double
  * thread in workgroups of up to 1024 threads or 32 in workgroups of up to
  * 768, minimal or doubled workgroup; for the lengths with a
  * register-resident kernel (powers of two 1024-8192; 200, 400, 800, 1000,
- * 1600, 2000, 4000, 5000, 8000, 10000) also that
+ * 1600, 2000, 2500, 4000, 5000, 8000, 10000) also that
  * kernel with table or power twiddles) on min(C, 16) channels of zeros,
  * keeps the fastest in the
  * plan, and, when the environment variable CWT_AUTOTUNE_CACHE names a file,

@@ -1,8 +1,8 @@
 // Register-resident FFT kernels for padded lengths that are not powers of two
 // (gfx950): L = 200 = 10 x 20, 400 = 20 x 20, 800 = 4 x 10 x 20,
-// 1000 = 5 x 20 x 10, 1600 = 4 x 20 x 20, 2000 = 5 x 20 x 20, 4000 =
-// 10 x 20 x 20, 5000 = 5 x 20 x 10 x 5, 8000 = 20 x 20 x 20 and 10000 =
-// 5 x 20 x 20 x 5.
+// 1000 = 5 x 20 x 10, 1600 = 4 x 20 x 20, 2000 = 5 x 20 x 20, 2500 =
+// 5 x 5 x 20 x 5, 4000 = 10 x 20 x 20, 5000 = 5 x 20 x 10 x 5, 8000 =
+// 20 x 20 x 20 and 10000 = 5 x 20 x 20 x 5.
 //
 // The scheme of the power-of-two kernels, generalised.  Every thread holds
 // V = 20 complex values in registers and every radix of the compile-time list
@@ -11,12 +11,13 @@
 // butterfly kb in v[kb + r V / R], and the strides and twiddle indexes of every
 // pass are compile-time constants.  Before a pass, v[m] is element t + T m of
 // its input; after the last, sample t + T m of the output (natural order).
-// Since T (10, 20, 40, 50, 80, 100, 200, 250, 400 or 500) is not a multiple
-// of the 64-lane wave, a workgroup runs SUB transforms side by side, one per
-// group of T threads with its own LDS slab: 32 x 10 threads at L = 200,
-// 16 x 20 at 400, 8 x 40 at 800, 5 x 50 at 1000, 4 x 80 at 1600 and 3 x 100
-// at 2000 (5 waves, 4 at L = 1000); 2 x 200 at 4000 and one transform of 250,
-// 400 or 500 threads at 5000, 8000 and 10000 (4, 7 and 8 waves).
+// Since T (10, 20, 40, 50, 80, 100, 125, 200, 250, 400 or 500) is not a
+// multiple of the 64-lane wave, a workgroup runs SUB transforms side by side,
+// one per group of T threads with its own LDS slab: 32 x 10 threads at
+// L = 200, 16 x 20 at 400, 8 x 40 at 800, 5 x 50 at 1000, 4 x 80 at 1600 and
+// 3 x 100 at 2000 (5 waves, 4 at L = 1000); 2 x 125 at 2500 and 2 x 200 at
+// 4000; one transform of 250, 400 or 500 threads at 5000, 8000 and 10000
+// (4, 7 and 8 waves).
 //
 // Inverse kernel.  The wavelet spectrum of one frequency is non-zero only on
 // a band of K cyclically consecutive bins.  The first pass (radix R0, no
@@ -62,8 +63,8 @@ struct MSub {
                                  : (L == 1000) ? 5
                                  : (L == 1600) ? 4
                                  : (L == 2000) ? 3
-                                 : (L == 4000) ? 2
-                                               : 1;
+                                 : (L == 2500 || L == 4000) ? 2
+                                                            : 1;
 };
 
 // LDS slots.  The buffer after pass p holds element i at slot
@@ -78,7 +79,7 @@ struct MSub {
 // included): 2.5 and 2.2 conflict cycles per access summed over the two
 // buffers (ideal 2.0), against 3.7 and 2.9 for plain slots with radices
 // [5, 10, 20] and [5, 20, 20]; each slab stays within the LDS that keeps 4
-// (L = 1000, 5000), 3 (L = 200 to 2000) or 2 (L = 4000, 8000, 10000)
+// (L = 1000, 2500, 5000), 3 (L = 200 to 2000) or 2 (L = 4000, 8000, 10000)
 // workgroups on a CU.
 // At L = 800 and 1600 the first radix is 4 (its first pass is the one a band
 // of at most L / 4 bins skips, which covers the EEG bands there), whose
@@ -87,6 +88,10 @@ struct MSub {
 template <int L, int PASS>
 struct MPad {  // plain slots: the buffers the model left unpadded
     static constexpr int C = 0, P = L;
+};
+template <>
+struct MPad<2500, 2> {
+    static constexpr int C = 5, P = 500;
 };
 template <>
 struct MPad<5000, 2> {
@@ -527,7 +532,8 @@ struct MShape {
 // Waves per SIMD the register budget allows: four (at most 128 registers)
 // for complex and power rows with power twiddles, which with a workgroup's
 // LDS is 4 workgroups per CU at L = 1000 (16 waves), 3 at L = 200 to 2000
-// (15), 2 of 7 waves at 4000 and 8000, 4 of 4 at 5000 and 2 of 8 at 10000;
+// (15), 2 of 7 waves at 4000 and 8000, 4 of 4 at 2500 and 5000 and 2 of 8 at
+// 10000;
 // three for band rows (20 running sums) and for table twiddles (their loads
 // are issued early), which would otherwise spill.
 template <int MODE, int TWM>
@@ -657,7 +663,7 @@ hipError_t launch_mixed_forward_t(const FwdParams &f, hipStream_t s)
 bool mixed_main_available(int L)
 {
     return L == 200 || L == 400 || L == 800 || L == 1000 || L == 1600 || L == 2000 ||
-           L == 4000 || L == 5000 || L == 8000 || L == 10000;
+           L == 2500 || L == 4000 || L == 5000 || L == 8000 || L == 10000;
 }
 
 int mixed_block_threads(int L)
@@ -670,6 +676,7 @@ int mixed_block_threads(int L)
     case 1600: return MShape<4, 20, 20>::threads;
     case 2000: return MShape<5, 20, 20>::threads;
     case 4000: return MShape<10, 20, 20>::threads;
+    case 2500: return MShape<5, 5, 20, 5>::threads;
     case 5000: return MShape<5, 20, 10, 5>::threads;
     case 8000: return MShape<20, 20, 20>::threads;
     case 10000: return MShape<5, 20, 20, 5>::threads;
@@ -685,7 +692,7 @@ int reg_schedule(int L, bool band, int *radix, int *threads)
                      p8192[] = {16, 16, 16, 2}, m200[] = {10, 20}, m400[] = {20, 20},
                      m800[] = {4, 10, 20}, m1000[] = {5, 20, 10},
                      m1600[] = {4, 20, 20}, m2000[] = {5, 20, 20}, m4000[] = {10, 20, 20},
-                     m5000[] = {5, 20, 10, 5}, m8000[] = {20, 20, 20},
+                     m2500[] = {5, 5, 20, 5}, m5000[] = {5, 20, 10, 5}, m8000[] = {20, 20, 20},
                      m10000[] = {5, 20, 20, 5};
     const int *r = nullptr;
     int n = 0;
@@ -701,6 +708,7 @@ int reg_schedule(int L, bool band, int *radix, int *threads)
     case 1600: r = m1600, n = 3, *threads = MShape<4, 20, 20>::threads; break;
     case 2000: r = m2000, n = 3, *threads = MShape<5, 20, 20>::threads; break;
     case 4000: r = m4000, n = 3, *threads = MShape<10, 20, 20>::threads; break;
+    case 2500: r = m2500, n = 4, *threads = MShape<5, 5, 20, 5>::threads; break;
     case 5000: r = m5000, n = 4, *threads = MShape<5, 20, 10, 5>::threads; break;
     case 8000: r = m8000, n = 3, *threads = MShape<20, 20, 20>::threads; break;
     case 10000: r = m10000, n = 4, *threads = MShape<5, 20, 20, 5>::threads; break;
@@ -721,6 +729,7 @@ hipError_t launch_main_mixed(const MainParams &p, hipStream_t s, LaunchEvents ev
     case 1600: return launch_mixed_main_v<4, 20, 20>(p, s, ev);
     case 2000: return launch_mixed_main_v<5, 20, 20>(p, s, ev);
     case 4000: return launch_mixed_main_v<10, 20, 20>(p, s, ev);
+    case 2500: return launch_mixed_main_v<5, 5, 20, 5>(p, s, ev);
     case 5000: return launch_mixed_main_v<5, 20, 10, 5>(p, s, ev);
     case 8000: return launch_mixed_main_v<20, 20, 20>(p, s, ev);
     case 10000: return launch_mixed_main_v<5, 20, 20, 5>(p, s, ev);
@@ -739,6 +748,7 @@ hipError_t launch_forward_mixed(const FwdParams &f, hipStream_t s)
     case 1600: return launch_mixed_forward_t<4, 20, 20>(f, s);
     case 2000: return launch_mixed_forward_t<5, 20, 20>(f, s);
     case 4000: return launch_mixed_forward_t<10, 20, 20>(f, s);
+    case 2500: return launch_mixed_forward_t<5, 5, 20, 5>(f, s);
     case 5000: return launch_mixed_forward_t<5, 20, 10, 5>(f, s);
     case 8000: return launch_mixed_forward_t<20, 20, 20>(f, s);
     case 10000: return launch_mixed_forward_t<5, 20, 20, 5>(f, s);
@@ -759,6 +769,7 @@ hipError_t launch_fused_mixed(const MainParams &p, const FwdParams &f, hipStream
     case 1600: return launch_mixed_fused_v<4, 20, 20>(p, f, s, ev);
     case 2000: return launch_mixed_fused_v<5, 20, 20>(p, f, s, ev);
     case 4000: return launch_mixed_fused_v<10, 20, 20>(p, f, s, ev);
+    case 2500: return launch_mixed_fused_v<5, 5, 20, 5>(p, f, s, ev);
     case 5000: return launch_mixed_fused_v<5, 20, 10, 5>(p, f, s, ev);
     case 8000: return launch_mixed_fused_v<20, 20, 20>(p, f, s, ev);
     case 10000: return launch_mixed_fused_v<5, 20, 20, 5>(p, f, s, ev);

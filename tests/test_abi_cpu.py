@@ -177,13 +177,14 @@ def test_fewest_three_factor_composites_among_ties(L, radix, threads, monkeypatc
     (2400, "power", 0, None, None), (400, "complex64", 1, [20, 20], 320),
     (200, "power", 1, [10, 20], 320), (4000, "complex64", 1, [10, 20, 20], 400),
     (8000, "bandpower", 1, [20, 20, 20], 400), (5000, "power", 1, [5, 20, 10, 5], 250),
-    (10000, "complex64", 1, [5, 20, 20, 5], 500)])
+    (10000, "complex64", 1, [5, 20, 20, 5], 500), (2500, "power", 1, [5, 5, 20, 5], 250)])
 def test_register_kernel_schedule(L, out, kernel, radix, threads):
     """Lengths with a register-resident kernel (powers of two 1024-8192, and
     the mixed-radix 200 = 10*20, 400 = 20*20, 800 = 4*10*20, 1000 =
-    5*20*10, 1600 = 4*20*20, 2000 = 5*20*20, 4000 = 10*20*20, 5000 =
-    5*20*10*5, 8000 = 20*20*20 and 10000 = 5*20*20*5 with 20 values per
-    thread and 32, 16, 8, 5, 4, 3, 2 or 1 transforms per workgroup) select it and describe its own passes and workgroup; others
+    5*20*10, 1600 = 4*20*20, 2000 = 5*20*20, 2500 = 5*5*20*5, 4000 =
+    10*20*20, 5000 = 5*20*10*5, 8000 = 20*20*20 and 10000 = 5*20*20*5 with
+    20 values per thread and 32, 16, 8, 5, 4, 3, 2 or 1 transforms per
+    workgroup) select it and describe its own passes and workgroup; others
     take the runtime-radix kernel."""
     freqs = synth.log_freqs(1.0, 100.0, 20)
     d = cwt.describe(L, 1000.0, freqs, n_cycles=synth.eeg_cycles(freqs), pad="explicit",

@@ -443,7 +443,8 @@ def test_band_path_edges(L, out):
                                              (1600, "fp32", "complex64"), (800, "fp32", "bandpower"),
                                              (400, "fp32", "power"), (200, "fp32", "complex64"),
                                              (4000, "fp32", "complex64"), (8000, "fp32", "bandpower"),
-                                             (5000, "fp32", "power"), (10000, "fp32", "complex64")])
+                                             (5000, "fp32", "power"), (10000, "fp32", "complex64"),
+                                             (2500, "fp32", "bandpower")])
 def test_execute_batches_matches_execute(n, precision, out):
     """cwt_execute_batches gives, batch for batch, exactly cwt_execute's
     output: with the register-resident kernels (L = 4096 and the mixed-radix
@@ -456,8 +457,8 @@ def test_execute_batches_matches_execute(n, precision, out):
     x = torch.from_numpy(d["x"]).cuda().view(nb, C, -1)
     plan = cwt.Plan(n, d["sfreq"], d["freqs"], n_cycles=d["n_cycles"], precision=precision,
                     out=out)
-    assert plan.desc.kernel == (1 if n in (200, 400, 800, 1000, 1600, 2000, 4000, 4096, 5000,
-                                           8000, 10000) else 0)
+    assert plan.desc.kernel == (1 if n in (200, 400, 800, 1000, 1600, 2000, 2500, 4000, 4096,
+                                           5000, 8000, 10000) else 0)
     refs = [plan.execute(x[i]).clone() for i in range(nb)]
     outb = torch.stack([torch.empty_like(refs[0]) for _ in range(nb)])
     ws = plan.alloc_batches_workspace(C)
@@ -802,16 +803,16 @@ def test_launch_work_item_limit():
     plan.close()
 
 
-@pytest.mark.parametrize("L", [200, 400, 800, 1000, 1600, 2000, 4000, 5000, 8000, 10000])
+@pytest.mark.parametrize("L", [200, 400, 800, 1000, 1600, 2000, 2500, 4000, 5000, 8000, 10000])
 @pytest.mark.parametrize("out", ["complex64", "power", "bandpower"])
 def test_mixed_radix_register_kernel(L, out, monkeypatch):
     """Mixed-radix register-resident kernels (L = 200 = 10*20, 400 = 20*20,
-    800 = 4*10*20, 1000 = 5*20*10, 1600 = 4*20*20, 2000 = 5*20*20, 4000 =
-    10*20*20, 5000 = 5*20*10*5, 8000 = 20*20*20, 10000 = 5*20*20*5; 20
-    values per thread, 32, 16, 8, 5, 4, 3, 2 or 1 transforms per workgroup,
-    two to four passes): rows whose band fits in S = L / R0 bins
-    (R0 the first radix) replace the first pass by one product per element,
-    wider rows stage their band and run every pass.  The grid
+    800 = 4*10*20, 1000 = 5*20*10, 1600 = 4*20*20, 2000 = 5*20*20, 2500 =
+    5*5*20*5, 4000 = 10*20*20, 5000 = 5*20*10*5, 8000 = 20*20*20, 10000 =
+    5*20*20*5; 20 values per thread, 32, 16, 8, 5, 4, 3, 2 or 1 transforms
+    per workgroup, two to four passes): rows whose band fits in S = L / R0
+    bins (R0 the first radix) replace the first pass by one product per
+    element, wider rows stage their band and run every pass.  The grid
     mixes both kinds (and bands wrapping past bin 0), 5 channels (a forward
     pair past the last channel), a row count that is not a multiple of the
     transforms per workgroup and a ragged crop; every row against the oracle,
@@ -862,7 +863,8 @@ def test_mixed_radix_register_kernel(L, out, monkeypatch):
 @pytest.mark.parametrize("L,variant", [(1000, 0), (2000, 0), (1000, 1), (800, 0), (800, 1),
                                        (1600, 0), (1600, 1), (200, 0), (200, 1), (400, 0),
                                        (400, 1), (4000, 0), (4000, 1), (8000, 0), (8000, 1),
-                                       (5000, 0), (5000, 1), (10000, 0), (10000, 1)])
+                                       (5000, 0), (5000, 1), (10000, 0), (10000, 1),
+                                       (2500, 0), (2500, 1)])
 def test_mixed_radix_twiddle_variants_and_sizes(L, variant, monkeypatch):
     """Both twiddle methods of the mixed-radix kernels (table, powers), one
     channel (the forward's second channel absent) and 64 channels (many
