@@ -16,8 +16,8 @@
 // one per group of T threads with its own LDS slab: 32 x 10 threads at
 // L = 200, 16 x 20 at 400, 8 x 40 at 800, 5 x 50 at 1000, 4 x 80 at 1600 and
 // 3 x 100 at 2000 (5 waves, 4 at L = 1000); 2 x 125 at 2500 and 2 x 200 at
-// 4000; one transform of 250, 400 or 500 threads at 5000, 8000 and 10000
-// (4, 7 and 8 waves).
+// 4000 (4 and 7 waves); one transform of 250, 400 or 500 threads at 5000,
+// 8000 and 10000 (4, 7 and 8 waves).
 //
 // Inverse kernel.  The wavelet spectrum of one frequency is non-zero only on
 // a band of K cyclically consecutive bins.  The first pass (radix R0, no
@@ -79,12 +79,11 @@ struct MSub {
 // included): 2.5 and 2.2 conflict cycles per access summed over the two
 // buffers (ideal 2.0), against 3.7 and 2.9 for plain slots with radices
 // [5, 10, 20] and [5, 20, 20]; each slab stays within the LDS that keeps 4
-// (L = 1000, 2500, 5000), 3 (L = 200 to 2000) or 2 (L = 4000, 8000, 10000)
-// workgroups on a CU.
-// At L = 800 and 1600 the first radix is 4 (its first pass is the one a band
-// of at most L / 4 bins skips, which covers the EEG bands there), whose
-// stride-4 scatter no gap with P a multiple of T spreads: 4.0 and 4.3 in the
-// model against 4.8 and 6.1 for plain slots.
+// (L = 1000, 2500, 5000), 3 (the other lengths up to 2000) or 2 (L = 4000,
+// 8000, 10000) workgroups on a CU.  At L = 800 and 1600 the first radix is 4
+// (its first pass is the one a band of at most L / 4 bins skips, which covers
+// the EEG bands there), whose stride-4 scatter no gap with P a multiple of T
+// spreads: 4.0 and 4.3 in the model against 4.8 and 6.1 for plain slots.
 template <int L, int PASS>
 struct MPad {  // plain slots: the buffers the model left unpadded
     static constexpr int C = 0, P = L;
